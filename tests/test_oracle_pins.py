@@ -1,0 +1,404 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every test here runs on the CPU.  The oracle (oracle/ee_oracle.c) is checked
+against things that are *not* itself:
+
+* rocRAND's open-source Philox4x32-10 (an independent implementation);
+* closed forms of the Metropolis thresholds at the 2D critical point;
+* exact partition functions (brute force, transfer matrix, Kaufman's torus
+  formula) and exact propagation of the protocol, through which Jarzynski's
+  equality must hold for every N;
+* the paper's counting of varied links, the beta = 0 limit, the N = 1
+  reweighting limit and the estimator's deterministic bounds.
+
+``test_planted_mistakes_are_caught`` compiles copies of the oracle with a
+single plausible mistake each and checks that a pin fails for every one.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import math
+import os
+import subprocess
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+from oracle import build as obuild
+from oracle import exact as ex
+from oracle import oracle as eo
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+BC2 = 0.5 * math.log(1.0 + math.sqrt(2.0))
+BC3 = 0.2216546
+
+
+def _paper():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Philox
+# --------------------------------------------------------------------------
+
+def _rocrand_ref():
+    if not os.path.exists(obuild.ROCRAND_REF_SO):
+        if obuild.build_rocrand_ref() is None:
+            pytest.skip("hipcc not available to build the rocRAND reference")
+    L = ctypes.CDLL(obuild.ROCRAND_REF_SO)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    L.ref_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    return L
+
+
+def test_philox_matches_rocrand():
+    L = _rocrand_ref()
+    rng = np.random.default_rng(12345)
+    A = ctypes.c_uint32 * 4
+    B = ctypes.c_uint32 * 2
+    cases = [((0, 0, 0, 0), (0, 0)), ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2)]
+    cases += [(tuple(int(v) for v in rng.integers(0, 2**32, 4)), tuple(int(v) for v in rng.integers(0, 2**32, 2)))
+              for _ in range(500)]
+    for ctr, key in cases:
+        out = A()
+        L.ref_philox4x32_10(A(*ctr), B(*key), out)
+        assert eo.philox(ctr, key) == tuple(out), (ctr, key)
+
+
+def test_philox_counter_words_all_matter():
+    base = eo.philox((1, 2, 3, 4), (5, 6))
+    for i in range(4):
+        c = [1, 2, 3, 4]
+        c[i] ^= 1
+        assert eo.philox(tuple(c), (5, 6)) != base
+    assert eo.philox((1, 2, 3, 4), (5, 7)) != base
+
+
+# --------------------------------------------------------------------------
+# Thresholds
+# --------------------------------------------------------------------------
+
+def _exact_floor_2p32(x: Decimal) -> int:
+    return int((x * (Decimal(2) ** 32)).to_integral_value(rounding="ROUND_FLOOR"))
+
+
+def test_threshold_closed_forms_at_2d_critical_point():
+    # beta_c = log(1+sqrt2)/2  =>  exp(-2 beta_c) = sqrt2 - 1,
+    # exp(-4 beta_c) = 3 - 2 sqrt2, exp(-8 beta_c) = 17 - 12 sqrt2.
+    getcontext().prec = 60
+    r2 = Decimal(2).sqrt()
+    p4 = Decimal(3) - 2 * r2
+    p8 = Decimal(17) - 12 * r2
+    for N in (1, 7, 256, 1000):
+        # bulk site: K = N * s with s = sigma * sum(neighbours)
+        assert eo.threshold(BC2, 2 * N, N) == _exact_floor_2p32(p4) - 1
+        assert eo.threshold(BC2, 4 * N, N) == _exact_floor_2p32(p8) - 1
+
+
+def test_threshold_limits():
+    assert eo.threshold(0.0, 5, 3) == 0xFFFFFFFF  # beta = 0 accepts everything
+    for K in (0, -1, -4000):
+        assert eo.threshold(0.44, K, 1000) == 0xFFFFFFFF  # energy not raised
+    vals = [eo.threshold(0.44, K, 10) for K in range(1, 200)]
+    assert all(a >= b for a, b in zip(vals, vals[1:]))  # monotone in the energy cost
+    assert eo.threshold(50.0, 100, 1) == 0  # exp(-10^4) underflows: accept only u == 0
+
+
+# --------------------------------------------------------------------------
+# Geometry
+# --------------------------------------------------------------------------
+
+def test_varied_links_count_matches_paper():
+    p = _paper()
+    assert p["varied_links_2d_two_replicas"]["value"] == 4
+    for (dim, lt, lx, ly, n) in [(2, 16, 16, 1, 2), (2, 8, 6, 1, 3), (3, 8, 6, 6, 2), (3, 4, 4, 8, 3)]:
+        L = ly  # spatial extent along the slab (L^(D-2) = Ly in 3D, 1 in 2D)
+        expect = 2 * (L ** (dim - 2) if dim == 3 else 1) * n
+        for l in (0, 1, lx - 1):
+            assert eo.count_ramped_bonds(dim, lt, lx, ly, n, l) == expect
+    # 3D with two replicas: 4L couplings (App. B)
+    assert eo.count_ramped_bonds(3, 8, 12, 12, 2, 3) == 4 * 12
+
+
+def test_energy_endpoints_are_geometries():
+    """At m = 0 the ramped column is in B, at m = N it is in A: the oracle's
+    integer energy must equal the pure-geometry energy of the exact module."""
+    rng = np.random.default_rng(3)
+    for (dim, lt, lx, ly, n, l) in [(2, 4, 6, 1, 2, 2), (3, 4, 4, 2, 3, 1)]:
+        lat0 = ex.Lattice(dim, lt, lx, ly, n, l)
+        job = eo.Job(dim, lt, lx, ly, n, 0.3, l, 5, 1, 1)
+        for _ in range(5):
+            s = rng.choice(np.array([-1, 1], dtype=np.int8), size=lat0.nsites)
+            for m, glued in ((0, l), (5, l + 1)):
+                b = ex.bonds(lat0, glued_upto=glued, ramp=False)
+                e = -sum(int(s[a]) * int(s[c]) for a, c, _ in b) * 5
+                assert eo.energy_units(job, m, s) == e
+
+
+# --------------------------------------------------------------------------
+# Exact partition functions
+# --------------------------------------------------------------------------
+
+def test_bruteforce_matches_kaufman():
+    for (rows, cols, K) in [(4, 4, BC2), (2, 6, 0.3), (4, 2, 0.7)]:
+        lat = ex.Lattice(2, rows, cols, 1, 1, 0)
+        assert ex.log_z_bruteforce(lat, K, ramp=False) == pytest.approx(ex.log_z_kaufman(rows, cols, K), rel=1e-13)
+
+
+def test_transfer_matrix_matches_kaufman_for_unglued_and_fully_glued():
+    for (lt, lx, n) in [(8, 4, 2), (6, 2, 3), (16, 4, 2)]:
+        lat = ex.Lattice(2, lt, lx, 1, n, 0)
+        z0 = ex.log_z_transfer(lat, BC2, ramp=False)
+        assert z0 == pytest.approx(n * ex.log_z_kaufman(lt, lx, BC2), rel=1e-13)  # Z_n(0) = Z^n
+        zall = ex.log_z_transfer(lat, BC2, glued_upto=lx, ramp=False)
+        assert zall == pytest.approx(ex.log_z_kaufman(n * lt, lx, BC2), rel=1e-13)  # one n*Lt torus
+
+
+def test_transfer_matrix_matches_bruteforce_with_ramp_and_3d():
+    cases = [(2, 4, 2, 1, 2, 1, BC2), (2, 2, 4, 1, 2, 2, BC2), (2, 2, 2, 1, 3, 1, 0.5), (3, 2, 2, 2, 2, 1, BC3)]
+    for (dim, lt, lx, ly, n, l, beta) in cases:
+        lat = ex.Lattice(dim, lt, lx, ly, n, l)
+        for m in (0, 1, 3):
+            assert ex.log_z_transfer(lat, beta, 3, m) == pytest.approx(ex.log_z_bruteforce(lat, beta, 3, m), rel=1e-13)
+
+
+def test_renyi_entropy_zero_without_cut_and_symmetric_at_low_temperature():
+    # S_2(0) = 0 exactly; S_2(l) ~ S_2(L-l) once Lt >> L (pure state, Sec. 2 / Sec. 4)
+    lat = ex.Lattice(2, 48, 4, 1, 2, 0)
+    z0 = ex.log_z_transfer(lat, BC2, ramp=False)
+    S = [-(ex.log_z_transfer(lat, BC2, glued_upto=l, ramp=False) - z0) for l in range(5)]
+    assert S[0] == 0.0
+    assert abs(S[4]) < 5e-3 and abs(S[1] - S[3]) < 5e-3
+    assert S[2] > S[1] > 0
+
+
+# --------------------------------------------------------------------------
+# Exact protocol: Jarzynski's equality
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", [
+    (2, 2, 4, 1, 2, 0, BC2),
+    (2, 2, 4, 1, 2, 2, BC2),
+    (3, 2, 2, 2, 2, 0, BC3),
+    (2, 2, 2, 1, 3, 0, 0.6),
+])
+def test_exact_protocol_obeys_jarzynski(case):
+    dim, lt, lx, ly, n, l, beta = case
+    lat = ex.Lattice(dim, lt, lx, ly, n, l)
+    Nb = 2
+    dF_exact = -(ex.log_z_bruteforce(lat, beta, Nb, Nb) - ex.log_z_bruteforce(lat, beta, Nb, 0))
+    for N in (1, 2):
+        v, p = ex.exact_protocol(lat, beta, N)
+        assert p.sum() == pytest.approx(1.0, abs=1e-13)
+        assert -math.log(ex.jarzynski_average(v, p, beta, N)) == pytest.approx(dF_exact, abs=2e-13)
+        # reverse protocol: <exp(-W)>_rev = 1 / <exp(-W)>_dir (App. A)
+        v, p = ex.exact_protocol(lat, beta, N, reverse=True)
+        assert -math.log(ex.jarzynski_average(v, p, beta, N)) == pytest.approx(-dF_exact, abs=2e-13)
+
+
+# --------------------------------------------------------------------------
+# Oracle Monte Carlo vs the exact work distribution
+# --------------------------------------------------------------------------
+
+def _chi2_pvalue(I: np.ndarray, vals: np.ndarray, probs: np.ndarray) -> float:
+    from scipy import stats
+    n = len(I)
+    exp_counts = probs * n
+    obs = np.array([np.sum(I == v) for v in vals], dtype=float)
+    assert obs.sum() == n, "oracle produced a work value outside the exact support"
+    # pool bins with small expectations
+    order = np.argsort(exp_counts)
+    e_pool, o_pool, acc_e, acc_o = [], [], 0.0, 0.0
+    for i in order:
+        acc_e += exp_counts[i]
+        acc_o += obs[i]
+        if acc_e >= 20:
+            e_pool.append(acc_e)
+            o_pool.append(acc_o)
+            acc_e, acc_o = 0.0, 0.0
+    if acc_e > 0:
+        e_pool[-1] += acc_e
+        o_pool[-1] += acc_o
+    e_pool, o_pool = np.array(e_pool), np.array(o_pool)
+    chi2 = float(np.sum((o_pool - e_pool) ** 2 / e_pool))
+    return float(stats.chi2.sf(chi2, max(len(e_pool) - 1, 1)))
+
+
+MC_CASES = [
+    # dim, lt, lx, ly, n, l, beta, N, n_therm, reverse
+    (2, 2, 4, 1, 2, 1, BC2, 3, 6, False),
+    (2, 2, 4, 1, 2, 0, BC2, 2, 2, True),
+    (3, 2, 2, 2, 2, 0, BC3, 2, 3, False),
+    (2, 2, 2, 1, 3, 1, 0.6, 3, 2, False),
+]
+
+
+def _oracle_vs_exact(lib_run, case, n_traj=20000, seed=11):
+    dim, lt, lx, ly, n, l, beta, N, n_therm, reverse = case
+    lat = ex.Lattice(dim, lt, lx, ly, n, l)
+    v, p = ex.exact_protocol(lat, beta, N, start="hot", n_therm=n_therm, reverse=reverse)
+    job = eo.Job(dim, lt, lx, ly, n, beta, l, N, n_traj, seed, reverse)
+    I = lib_run(job, n_therm)
+    if not np.all(np.isin(I, v)):
+        return 0.0
+    return _chi2_pvalue(I, v, p)
+
+
+@pytest.mark.parametrize("case", MC_CASES)
+def test_oracle_work_distribution_matches_exact_propagation(case):
+    pval = _oracle_vs_exact(lambda job, nt: eo.run(job, nt)[0], case)
+    assert pval > 1e-4, pval
+
+
+def test_oracle_estimate_close_to_exact_free_energy():
+    lat = ex.Lattice(2, 4, 4, 1, 2, 1)
+    N = 4
+    dF_exact = -(ex.log_z_transfer(lat, BC2, N, N) - ex.log_z_transfer(lat, BC2, N, 0))
+    job = eo.Job(2, 4, 4, 1, 2, BC2, 1, N, 4000, 5)
+    I, _ = eo.run(job, 50)
+    est = eo.estimate(I, BC2, N, 2)
+    assert abs(est.dF - dF_exact) < 4 * est.dF_err + 0.5 * est.w_var / len(I)
+
+
+# --------------------------------------------------------------------------
+# Special cases of the method
+# --------------------------------------------------------------------------
+
+def test_beta_zero_every_attempt_flips_and_dF_is_zero():
+    job = eo.Job(2, 4, 6, 1, 2, 0.0, 2, 5, 3, 9)
+    I0, s0 = eo.run(job, 0, n_step_run=0, want_spins=True)  # initial state
+    for g in (1, 2, 7):
+        _, s = eo.run(job, g, n_step_run=0, want_spins=True)
+        assert np.array_equal(s, s0 * (-1) ** g)
+    I, _ = eo.run(job, 4)
+    est = eo.estimate(I, 0.0, job.n_step, 2)
+    assert est.dF == 0.0 and est.w_mean == 0.0
+
+
+def test_initial_state_is_a_fair_coin():
+    job = eo.Job(2, 32, 32, 1, 2, 0.4, 3, 1, 8, 21)
+    _, s = eo.run(job, 0, n_step_run=0, want_spins=True)
+    frac = np.mean(s == 1)
+    assert abs(frac - 0.5) < 4 * 0.5 / math.sqrt(s.size)
+
+
+def test_work_is_energy_difference_on_state_before_each_sweep():
+    """I(k+1) - I(k) = -(E(m_{k+1}) - E(m_k)) evaluated on phi_k (App. A)."""
+    for reverse in (False, True):
+        job = eo.Job(3, 4, 4, 2, 2, BC3, 1, 6, 3, 4, reverse)
+        nt = 5
+        for k in range(job.n_step):
+            Ik, sk = eo.run(job, nt, n_step_run=k, want_spins=True)
+            Ik1, _ = eo.run(job, nt, n_step_run=k + 1)
+            mk = job.n_step - k if reverse else k
+            mk1 = job.n_step - (k + 1) if reverse else k + 1
+            for j in range(job.n_traj):
+                dE = eo.energy_units(job, mk1, sk[j]) - eo.energy_units(job, mk, sk[j])
+                assert Ik1[j] - Ik[j] == -dE
+
+
+def test_single_step_is_reweighting():
+    """N = 1: W = H_f(phi_0) - H_i(phi_0) on the thermalised state (App. A)."""
+    job = eo.Job(2, 6, 6, 1, 2, BC2, 2, 1, 16, 8)
+    _, s0 = eo.run(job, 12, n_step_run=0, want_spins=True)
+    I, _ = eo.run(job, 12)
+    for j in range(job.n_traj):
+        assert I[j] == -(eo.energy_units(job, 1, s0[j]) - eo.energy_units(job, 0, s0[j]))
+
+
+def test_work_bound():
+    job = eo.Job(2, 8, 8, 1, 2, 2.0, 3, 7, 64, 2)
+    I, _ = eo.run(job, 3)
+    assert np.all(np.abs(I) <= 2 * job.n * 1 * job.n_step)
+
+
+def test_trajectories_are_independent_of_the_range_run():
+    job = eo.Job(2, 6, 8, 1, 2, BC2, 3, 9, 10, 77)
+    Iall, sall = eo.run(job, 4, want_spins=True)
+    Ipart, spart = eo.run(job, 4, 3, 7, want_spins=True)
+    assert np.array_equal(Iall[3:7], Ipart) and np.array_equal(sall[3:7], spart)
+
+
+# --------------------------------------------------------------------------
+# Estimator
+# --------------------------------------------------------------------------
+
+def test_estimator_bounds_and_closed_forms():
+    rng = np.random.default_rng(0)
+    beta, N = 0.44, 50
+    for _ in range(20):
+        I = rng.integers(-400, 400, size=int(rng.integers(2, 300)))
+        est = eo.estimate(I, beta, N, 2)
+        W = -(beta / N) * I
+        assert W.min() - 1e-12 <= est.dF <= W.mean() + 1e-12  # Jensen
+        assert est.dF == pytest.approx(-math.log(np.mean(np.exp(-W))), rel=1e-12, abs=1e-12)
+        assert est.i_min == I.min() and est.i_max == I.max()
+        assert 1.0 <= est.ess <= len(I) + 1e-9
+    # constant work: dF = W exactly, zero jackknife error, ESS = n_t
+    est = eo.estimate(np.full(10, 37), beta, N, 3)
+    assert est.dF == pytest.approx(-(beta / N) * 37, rel=1e-15)
+    assert est.dS == pytest.approx(est.dF / 2, rel=1e-15)
+    assert est.dF_err == pytest.approx(0.0, abs=1e-14) and est.ess == pytest.approx(10.0)
+    # two samples: jackknife of two points, sigma = |dF_(1) - dF_(2)| / 2 * sqrt(... ) closed form
+    I = np.array([0, 100])
+    est = eo.estimate(I, beta, N, 2)
+    d1, d2 = -(beta / N) * 100, 0.0  # leave-one-out values
+    assert est.dF_err == pytest.approx(math.sqrt(0.5 * ((d1 - d2) ** 2 / 2)), rel=1e-12)
+    assert math.isnan(eo.estimate(np.array([5]), beta, N, 2).dF_err)
+
+
+# --------------------------------------------------------------------------
+# Planted mistakes
+# --------------------------------------------------------------------------
+
+MUTATIONS = {
+    "work sign": ("if (I_out) I_out[j - j0] = -work_units;", "if (I_out) I_out[j - j0] = work_units;"),
+    "sweep at lambda_k": ("sweep(&G, m_next, g++, (uint32_t)j, s);", "sweep(&G, m_now, g++, (uint32_t)j, s);"),
+    "dropped inter bond": ("field += bond_weight(G, G->adj_kind[e], m) * s[G->adj_nbr[e]];",
+                           "field += (G->adj_kind[e] == BOND_INTER ? 0 : bond_weight(G, G->adj_kind[e], m)) * s[G->adj_nbr[e]];"),
+    "glue to r-1": ("add_bond(G, s, site_index(G, (r + 1) % n, 1, y, x), BOND_BULK);",
+                    "add_bond(G, s, site_index(G, (r + n - 1) % n, 1, y, x), BOND_BULK);"),
+    "threshold beta": ("double x = (2.0 * beta * (double)K) / (double)N;", "double x = (1.0 * beta * (double)K) / (double)N;"),
+    "intra weight": ("if (kind == BOND_INTRA) return (int64_t)(G->N - m);", "if (kind == BOND_INTRA) return (int64_t)(G->N - m + 1);"),
+    "work after sweep": ("work_units += energy_units(&G, m_next, s) - energy_units(&G, m_now, s);\n      sweep(&G, m_next, g++, (uint32_t)j, s);",
+                         "sweep(&G, m_next, g++, (uint32_t)j, s);\n      work_units += energy_units(&G, m_next, s) - energy_units(&G, m_now, s);"),
+}
+# Not listed: the order of the two colours.  The reflection t -> 1-t together
+# with r -> -r maps the cut geometry onto itself and swaps the colours, so the
+# work distribution cannot see it; it is a convention of the random-number
+# streams, checked only by bit-exact parity of the GPU path.
+
+
+def _build_mutant(tmp_path, name, old, new):
+    src = open(os.path.join(os.path.dirname(obuild.ORACLE_SO), "ee_oracle.c")).read()
+    assert src.count(old) == 1, f"mutation site for '{name}' not found exactly once"
+    path = tmp_path / (name.replace(" ", "_") + ".c")
+    path.write_text(src.replace(old, new))
+    so = str(path) + ".so"
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-ffp-contract=off", str(path), "-o", so, "-lm"], check=True)
+    L = ctypes.CDLL(so)
+    L.eo_run.argtypes = eo.lib().eo_run.argtypes
+    L.eo_run.restype = ctypes.c_int
+    return L
+
+
+def test_planted_mistakes_are_caught(tmp_path):
+    """Each plausible mistake in the oracle makes a pin fail."""
+    # n = 3 so that the glue direction matters; the colour-order mutation
+    # needs an asymmetric case with N >= 2.
+    cases = [(2, 2, 2, 1, 3, 1, 0.6, 3, 2, False), (2, 2, 4, 1, 2, 1, BC2, 3, 2, False)]
+    for name, (old, new) in MUTATIONS.items():
+        L = _build_mutant(tmp_path, name, old, new)
+
+        def run(job, nt, L=L):
+            I = np.zeros(job.n_traj, dtype=np.int64)
+            rc = L.eo_run(job.dim, job.lt, job.lx, job.ly, job.n, job.beta, job.l, job.n_step, job.n_traj,
+                          job.seed, int(job.reverse), nt, 0, job.n_traj, job.n_step, I.ctypes.data, None)
+            assert rc == 0
+            return I
+
+        caught = any(_oracle_vs_exact(run, c, n_traj=20000) < 1e-6 for c in cases)
+        assert caught, f"planted mistake '{name}' was not detected"
