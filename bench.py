@@ -1,0 +1,171 @@
+"""Benchmark: spin-flip attempts/ns of the non-equilibrium Renyi-entropy
+estimator on one MI355X.
+
+Workload (one step): the 2D 64x64 job set -- 64 jobs l = 0..63 (S_2 for
+l = 1..64), n = 2, beta_c, N = 1000 protocol sweeps after 100 thermalisation
+sweeps, 1024 trajectories per job, int8 spins -- run through the persistent
+batched path (one fused sweep+work launch over all 65536 trajectories, then
+the estimator launch), followed by the host assembly of S_2(l) and C_2(x).
+Inputs are synthetic (the job descriptions); every spin and uniform is drawn
+on the device.
+
+Prints one JSON line.  --gpus N > 1 is not supported (one-GPU build).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 32-bit VALU lane-ops/s.
+PEAK_INT_LANE_OPS = 256 * 4 * 16 * 2.4e9
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_2d64_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_03311_amd", "csrc", f) for f in ("ee_kernels.hip", "ee_internal.hpp")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def ops_per_attempt(dim: int) -> float:
+    """Algorithmic 32-bit integer VALU operations per Metropolis attempt.
+
+    A quarter of one Philox4x32-10 call (10 rounds of 2 multiply-high, 2
+    multiply-low and 4 xor = 80 ops per call, 4 uniforms) = 20, plus the
+    update of 4 same-colour sites sharing one 32-bit word: 2*dim xor and
+    2*dim-1 add for the anti-aligned counts (shared by 4 sites), and per site
+    byte extract, threshold select (dim compares+selects), compare, flip-bit
+    insert.  See the roofline section of the design notes."""
+    philox = 80.0 / 4.0
+    counts = (2 * dim + 2 * dim - 1) / 4.0
+    per_site = 1 + 2 * dim + 1 + 2
+    return philox + counts + per_site
+
+
+def cpu_baseline(n_traj_sample: int) -> dict:
+    from oracle import oracle as eo
+    from paper_2304_03311_amd import workloads
+    s = workloads.config2_jobs()[32]
+    job = eo.Job(s.dim, s.lt, s.lx, s.ly, s.n, s.beta, s.l, s.n_step, s.n_traj, s.seed)
+    t0 = time.perf_counter()
+    eo.run(job, workloads.N_THERM, 0, n_traj_sample)
+    dt = time.perf_counter() - t0
+    att = n_traj_sample * s.sites * (workloads.N_THERM + s.n_step)
+    return {"value": att / (dt * 1e9), "unit": "attempts/ns", "cores": 1, "kind": "oracle",
+            "sample": f"job l=32 of the 2D 64x64 set, trajectories 0..{n_traj_sample - 1} "
+                      f"({att:.3g} attempts, {dt:.1f} s, single-threaded C oracle)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=32, help="oracle trajectories timed for cpu_baseline")
+    ap.add_argument("--per-job", action="store_true", help="also time the per-job launch path")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build runs on one GPU "
+              f"(trajectories shard across GPUs by index; no multi-GPU path is built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2304_03311_amd import analysis, ee, workloads
+
+    torch.cuda.set_device(0)
+    specs = workloads.config2_jobs()
+    stream = torch.cuda.current_stream()
+    jobs = [ee.Job(s, stream=stream) for s in specs]
+    n_therm = workloads.N_THERM
+    attempts_per_step = sum(s.n_traj * s.sites * (n_therm + s.n_step) for s in specs)
+
+    def step():
+        for j in jobs:
+            j.reset()
+        ee.batch_run(jobs, n_therm, stream=stream, cfg=workloads.BENCH_LAUNCH)
+        res = [j.estimate() for j in jobs]
+        return res, ee.ee_batch_kernel_ms()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, kms = step()
+        kernel_ms.append(kms)
+        curve = analysis.assemble([r.dS for r in res], [r.dF_err for r in res], L=64, dim=2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    ms_per_step = dt * 1e3 / args.steps
+    value = attempts_per_step * args.steps / (dt * 1e9)
+    k_avg_s = float(np.mean(kernel_ms)) * 1e-3
+    ops = ops_per_attempt(2) * attempts_per_step
+    achieved = ops / k_avg_s / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+    out = {
+        "metric": "spin-flip attempts/ns",
+        "value": value,
+        "unit": "attempts/ns",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8 spins, uint32 RNG/thresholds, int32 work, fp64 estimator",
+        "data": "synthetic (seeded job descriptions; spins and uniforms drawn on device)",
+        "config": {"workload": "2D Ising 64x64, n=2, beta_c, l=0..63 (64 jobs), N=1000, "
+                               "N_therm=100, n_t=1024, int8, persistent batched path",
+                   "jobs": len(specs), "trajectories": sum(s.n_traj for s in specs),
+                   "attempts_per_step": attempts_per_step, "parallelism": "1 GPU"},
+        "jobs_per_s": len(specs) * args.steps / dt,
+        "dS2_err_median": float(np.median([r.dF_err for r in res])),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_LANE_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / (PEAK_INT_LANE_OPS / 1e12), "traffic": traffic,
+                     "kernel": "sweep_kernel (persistent)", "kernel_ms": k_avg_s * 1e3,
+                     "ops_per_attempt": ops_per_attempt(2),
+                     "attempts_per_ns_in_kernel": attempts_per_step / (k_avg_s * 1e9)},
+        "c2_fit_k": curve.get("fit_k"),
+    }
+    if args.per_job:
+        t0 = time.perf_counter()
+        for j in jobs:
+            j.reset()
+            j.thermalize(n_therm)
+            j.run_protocol()
+        for j in jobs:
+            j.estimate()
+        torch.cuda.synchronize()
+        out["per_job_path_attempts_per_ns"] = attempts_per_step / ((time.perf_counter() - t0) * 1e9)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    for j in jobs:
+        j.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

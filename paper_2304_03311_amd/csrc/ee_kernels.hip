@@ -1,0 +1,497 @@
+// ee_kernels.hip -- gfx950 kernels of the non-equilibrium Renyi-entropy
+// estimator (Bulgarelli & Panero, arXiv:2304.03311).
+//
+// sweep_kernel<DIM>: one workgroup holds k trajectories of one job in LDS
+//   (int8 spins, colour-separated rows) and runs, entirely on chip, the
+//   initial spins, the thermalisation sweeps and the N protocol sweeps with
+//   the integer work (Sec. 3 linear protocol; App. A work-then-update).
+//   One lane updates one 32-bit word = 4 same-colour sites of a row with one
+//   Philox4x32-10 call (one 32-bit uniform per site) and an integer compare
+//   against a uint32 threshold per site.  In batch mode the workgroups are
+//   persistent and pull work units (job, block of trajectories) from a
+//   device queue.
+// estimate_kernel: Jarzynski estimator of one job per workgroup (App. A):
+//   integer max/min/sum of I_j, FP64 sum of exp(beta (I_j - I_max)/N),
+//   log-sum-exp, delete-one jackknife from prefix/suffix sums.
+#include <hip/hip_runtime.h>
+
+#include "ee_internal.hpp"
+
+namespace {
+
+using ee::JobDev;
+using ee::Unit;
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+  uint64_t v = reinterpret_cast<uint64_t>(p);
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mul, uint32_t shift) {
+  return (__umulhi(n, mul) + n) >> shift;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products.
+__device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// Per-job constants, held in scalar registers.
+struct JP {
+  int dim, n, lt, ly, l, N, H, G, R, traj_words, packed_row_words;
+  uint32_t key0, key1, thr0, thr1, thr2, reverse, spin_format;
+  uint32_t mR, sR, mLy, sLy;
+  const uint32_t* ramp;
+  uint32_t* spins;
+  int64_t* work;
+};
+
+__device__ __forceinline__ JP load_jp(const JobDev* J) {
+  JP P;
+  P.dim = uni(J->dim);
+  P.n = uni(J->n); P.lt = uni(J->lt); P.ly = uni(J->ly); P.l = uni(J->l); P.N = uni(J->N);
+  P.H = uni(J->H); P.G = uni(J->G); P.R = uni(J->R); P.traj_words = uni(J->traj_words);
+  P.packed_row_words = (P.H + 31) >> 5;
+  P.key0 = uni(J->key0); P.key1 = uni(J->key1);
+  P.thr0 = uni(J->thr_bulk[0]); P.thr1 = uni(J->thr_bulk[1]); P.thr2 = uni(J->thr_bulk[2]);
+  P.reverse = uni(J->reverse); P.spin_format = uni(J->spin_format);
+  P.mR = uni(J->magic_R); P.sR = uni(J->shift_R); P.mLy = uni(J->magic_Ly); P.sLy = uni(J->shift_Ly);
+  P.ramp = uni_ptr(J->ramp_thr);
+  P.spins = uni_ptr(J->spins);
+  P.work = uni_ptr(J->work);
+  return P;
+}
+
+// Accept bits of the 4 bulk/glued sites of a word: a holds the number of
+// anti-aligned neighbours per byte (0..2*DIM).  The energy cost is
+// 2*beta*(2*DIM - 2a); a >= DIM never raises the energy.
+template <int DIM>
+__device__ __forceinline__ uint32_t decide(uint32_t a, const uint32_t u[4], const JP& P) {
+  uint32_t f = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t ai = (a >> (8 * i)) & 0xFFu;
+    uint32_t thr;
+    if (DIM == 2) {
+      thr = (ai == 0) ? P.thr0 : ((ai == 1) ? P.thr1 : 0xFFFFFFFFu);
+    } else {
+      thr = (ai == 0) ? P.thr0 : ((ai == 1) ? P.thr1 : ((ai == 2) ? P.thr2 : 0xFFFFFFFFu));
+    }
+    f |= (uint32_t)(u[i] <= thr) << (8 * i);
+  }
+  return f;
+}
+
+// One half-sweep of colour c over the rows of one trajectory owned by this
+// lane (fixed word w, rows rg, rg+nrg, ...).  L: the trajectory in LDS.
+template <int DIM>
+__device__ __forceinline__ void half_sweep(const JP& P, uint32_t* __restrict__ L, const int c,
+                                           const int w, const int rg, const int nrg,
+                                           const uint32_t g, const uint32_t j, const int m,
+                                           const bool work, int& dI) {
+  const int cw = P.n * P.R * P.G;  // words per colour plane
+  uint32_t* __restrict__ Lc = L + c * cw;
+  const uint32_t* __restrict__ Lo = L + (c ^ 1) * cw;
+  const int nrows = P.n * P.R;
+  const int G = P.G;
+  const int wl = (w == 0) ? G - 1 : w - 1;
+  const int wr = (w == G - 1) ? 0 : w + 1;
+  const int tailsh = 8 * ((P.H - 1) & 3);
+  const uint32_t valid = (w == G - 1 && tailsh != 24) ? ((1u << (tailsh + 8)) - 1u) : 0xFFFFFFFFu;
+  const uint32_t rshift = (w == G - 1) ? (uint32_t)tailsh : 24u;
+  const uint32_t ctr3 = (1u << 28) | (uint32_t)c;
+  const int ramp_w = P.l >> 3;
+  const int ramp_p = P.l & 1;
+  const int ramp_sh = 8 * ((P.l >> 1) & 3);
+
+  for (int row = rg; row < nrows; row += nrg) {
+    const int r = (int)fdiv((uint32_t)row, P.mR, P.sR);
+    const int rho = row - r * P.R;
+    int t, y;
+    if (DIM == 3) {
+      t = (int)fdiv((uint32_t)rho, P.mLy, P.sLy);
+      y = rho - t * P.ly;
+    } else {
+      t = rho;
+      y = 0;
+    }
+    const int p = (c + t + y) & 1;  // x parity of this row's sites
+    const int rbase = r * P.R;
+    const int rowbase = (rbase + rho) * G;
+    const uint32_t S = Lc[rowbase + w];
+    const uint32_t A = Lo[rowbase + w];
+    uint32_t B;
+    if (p) {  // right neighbours x+1: half-index h+1
+      const uint32_t nb = Lo[rowbase + wr] & 0xFFu;
+      B = (A >> 8) | (nb << rshift);
+    } else {  // left neighbours x-1: half-index h-1
+      const uint32_t pd = Lo[rowbase + wl];
+      const uint32_t pb = (w == 0) ? ((pd >> tailsh) & 0xFFu) : (pd >> 24);
+      B = (A << 8) | pb;
+    }
+    const int tm = (t == 0) ? P.lt - 1 : t - 1;
+    const int tp = (t == P.lt - 1) ? 0 : t + 1;
+    const uint32_t Tm = Lo[(rbase + tm * P.ly + y) * G + w];
+    const uint32_t Tp = Lo[(rbase + tp * P.ly + y) * G + w];
+    uint32_t afix = (A ^ S) + (B ^ S);
+    if (DIM == 3) {
+      const int ym = (y == 0) ? P.ly - 1 : y - 1;
+      const int yp = (y == P.ly - 1) ? 0 : y + 1;
+      afix += (Lo[(rbase + t * P.ly + ym) * G + w] ^ S) + (Lo[(rbase + t * P.ly + yp) * G + w] ^ S);
+    }
+    uint32_t u[4];
+    philox10((uint32_t)(rho * G + w), g, j, ctr3 | ((uint32_t)r << 1), P.key0, P.key1, u);
+    uint32_t flip;
+    if (t > 1) {
+      flip = decide<DIM>(afix + (Tm ^ S) + (Tp ^ S), u, P) & valid;
+    } else {
+      // A row next to the cut: its temporal partner across the cut is in
+      // replica r+1 (t = 0) or r-1 (t = 1) for glued columns x < l.
+      const int rgl = (t == 0) ? ((r + 1 == P.n) ? 0 : r + 1) : ((r == 0) ? P.n - 1 : r - 1);
+      const uint32_t Tg = Lo[(rgl * P.R + (1 - t) * P.ly + y) * G + w];
+      const int v = P.l - p - 8 * w;  // bytes i with 8w + 2i + p < l are glued
+      const int ng = (v <= 0) ? 0 : ((v + 1) >> 1);
+      const uint32_t gm = (ng >= 4) ? 0xFFFFFFFFu : ((1u << (8 * ng)) - 1u);
+      const uint32_t Tcut = (t == 0) ? Tp : Tm;  // own-replica partner across the cut
+      const uint32_t Tfix = (t == 0) ? Tm : Tp;  // temporal neighbour away from the cut
+      afix += Tfix ^ S;
+      const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
+      flip = decide<DIM>(afix + (Teff ^ S), u, P) & valid;
+      if (p == ramp_p && w == ramp_w) {
+        // ramped site x = l: K = s (N a + (N-m) s_intra + m s_inter)
+        const uint32_t fa = (afix >> ramp_sh) & 0xFFu;
+        const uint32_t bb = ((Tcut ^ S) >> ramp_sh) & 1u;
+        const uint32_t cc = ((Tg ^ S) >> ramp_sh) & 1u;
+        const uint32_t U = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
+        const uint32_t uu = (ramp_sh == 0) ? u[0] : (ramp_sh == 8) ? u[1] : (ramp_sh == 16) ? u[2] : u[3];
+        flip = (flip & ~(0xFFu << ramp_sh)) | ((uint32_t)(uu <= U) << ramp_sh);
+        if (work) {
+          // the ramped site of colour 0 sees phi_k: D_k term = 2 (b - c)
+          const int d = 2 * ((int)bb - (int)cc);
+          dI += P.reverse ? -d : d;
+        }
+      }
+    }
+    Lc[rowbase + w] = S ^ flip;
+  }
+}
+
+// Initial spins (phase 0 of the Philox streams): +1 iff u < 2^31.
+__device__ void init_spins(const JP& P, uint32_t* L, uint32_t j, int lt_, int T) {
+  const int nR = P.n * P.R;
+  for (int q = lt_; q < P.traj_words; q += T) {
+    const int w = q % P.G;
+    const int rowg = q / P.G;
+    const int c = rowg / nR;
+    const int row = rowg - c * nR;
+    const int r = row / P.R;
+    const int rho = row - r * P.R;
+    uint32_t u[4];
+    philox10((uint32_t)(rho * P.G + w), 0u, j, ((uint32_t)r << 1) | (uint32_t)c, P.key0, P.key1, u);
+    uint32_t word = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * w + i < P.H) word |= (uint32_t)(u[i] < 0x80000000u) << (8 * i);
+    L[q] = word;
+  }
+}
+
+__device__ void load_spins(const JP& P, uint32_t* L, uint32_t j, int lt_, int T) {
+  if (P.spin_format == EE_SPINS_INT8) {
+    const uint32_t* src = P.spins + (size_t)j * P.traj_words;
+    for (int q = lt_; q < P.traj_words; q += T) L[q] = src[q];
+  } else {
+    const int PW = P.packed_row_words;
+    const uint32_t* src = P.spins + (size_t)j * (2 * P.n * P.R * PW);
+    for (int q = lt_; q < P.traj_words; q += T) {
+      const int w = q % P.G;
+      const int rowg = q / P.G;
+      const uint32_t nib = (src[rowg * PW + (w >> 3)] >> (4 * (w & 7))) & 0xFu;
+      L[q] = (nib * 0x00204081u) & 0x01010101u;  // 4 bits -> 4 bytes
+    }
+  }
+}
+
+__device__ void store_spins(const JP& P, const uint32_t* L, uint32_t j, int lt_, int T) {
+  if (P.spin_format == EE_SPINS_INT8) {
+    uint32_t* dst = P.spins + (size_t)j * P.traj_words;
+    for (int q = lt_; q < P.traj_words; q += T) dst[q] = L[q];
+  } else {
+    const int PW = P.packed_row_words;
+    const int total = 2 * P.n * P.R * PW;
+    uint32_t* dst = P.spins + (size_t)j * total;
+    for (int q = lt_; q < total; q += T) {
+      const int wb = q % PW;
+      const int rowg = q / PW;
+      uint32_t packed = 0;
+      for (int k = 0; k < 8; ++k) {
+        const int w = 8 * wb + k;
+        if (w < P.G) packed |= (((L[rowg * P.G + w] * 0x01020408u) >> 24) & 0xFu) << (4 * k);
+      }
+      dst[q] = packed;
+    }
+  }
+}
+
+// All sweeps of one work unit: k trajectories of one job, one per LDS slot.
+template <int DIM>
+__device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, int j0, int cnt, int kslots,
+                                         uint32_t flags, int n_therm, int g0) {
+  const int tid = threadIdx.x;
+  const int T = blockDim.x / kslots;
+  const int slot = tid / T;
+  const int lt_ = tid - slot * T;
+  const bool active = slot < cnt;
+  uint32_t* L = lds + (size_t)slot * P.traj_words;
+  const uint32_t j = (uint32_t)(j0 + slot);
+  if (tid < ee::kMaxSlots) s_dI[tid] = 0;
+  if (active) {
+    if (flags & ee::kFlagInit) init_spins(P, L, j, lt_, T);
+    else load_spins(P, L, j, lt_, T);
+  }
+  __syncthreads();
+
+  const int w = lt_ % P.G;
+  const int rg = lt_ / P.G;
+  const int nrg = T / P.G;
+  const bool on = active && rg < nrg;
+  int dI = 0;
+  uint32_t g = (uint32_t)g0;
+  const int m0 = P.reverse ? P.N : 0;
+  for (int s = 0; s < n_therm; ++s, ++g) {
+    if (on) half_sweep<DIM>(P, L, 0, w, rg, nrg, g, j, m0, false, dI);
+    __syncthreads();
+    if (on) half_sweep<DIM>(P, L, 1, w, rg, nrg, g, j, m0, false, dI);
+    __syncthreads();
+  }
+  if (flags & ee::kFlagProto) {
+    for (int k = 0; k < P.N; ++k, ++g) {
+      const int m = P.reverse ? P.N - 1 - k : k + 1;
+      if (on) half_sweep<DIM>(P, L, 0, w, rg, nrg, g, j, m, true, dI);
+      __syncthreads();
+      if (on) half_sweep<DIM>(P, L, 1, w, rg, nrg, g, j, m, false, dI);
+      __syncthreads();
+    }
+    if (dI != 0) atomicAdd(&s_dI[slot], dI);
+    __syncthreads();
+    if (active && lt_ == 0) P.work[j] = (int64_t)s_dI[slot];
+  }
+  if (active) store_spins(P, L, j, lt_, T);
+  __syncthreads();
+}
+
+// Per-job mode (units == nullptr): workgroup b runs trajectories
+// [b*single_k, b*single_k + single_k) of single_job.  Batch mode: persistent
+// workgroups draw units from the queue until it is empty.  The dimension of
+// each unit's job selects the 2D or 3D sweep (uniform per workgroup).
+__global__ void __launch_bounds__(1024)
+sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_units, int* queue,
+             const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int s_unit;
+  __shared__ int s_dI[ee::kMaxSlots];
+  const int tid = threadIdx.x;
+  for (int iter = 0;; ++iter) {
+    const JobDev* J;
+    int j0, cnt, kslots;
+    if (units != nullptr) {
+      if (tid == 0) s_unit = atomicAdd(queue, 1);
+      __syncthreads();
+      const int u = s_unit;
+      if (u >= n_units) break;
+      const Unit U = units[u];
+      J = uni_ptr(jobtab[uni(U.job)]);
+      j0 = uni(U.j0);
+      cnt = uni(U.count);
+      kslots = uni(U.slots);
+    } else {
+      if (iter > 0) break;
+      J = single_job;
+      kslots = single_k;
+      j0 = blockIdx.x * kslots;
+      cnt = min(kslots, J->n_traj - j0);
+    }
+    const JP P = load_jp(J);
+    if (uni(J->dim) == 3)
+      run_unit<3>(P, lds, s_dI, j0, cnt, kslots, flags, n_therm, g0);
+    else
+      run_unit<2>(P, lds, s_dI, j0, cnt, kslots, flags, n_therm, g0);
+  }
+}
+
+__global__ void queue_reset_kernel(int* queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Estimator
+// ---------------------------------------------------------------------------
+constexpr int kEstThreads = 256;
+
+template <typename T, typename Op>
+__device__ T block_reduce(T v, T* sh, Op op) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = kEstThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] = op(sh[tid], sh[tid + s]);
+    __syncthreads();
+  }
+  T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* const* jobtab) {
+  __shared__ double shd[kEstThreads];
+  __shared__ long long shl[kEstThreads];
+  __shared__ double pre[kEstThreads + 1];
+  __shared__ double suf[kEstThreads + 1];
+  const JobDev* J = jobtab[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int n = J->n_traj;
+  const int64_t* I = J->work;
+  const double beta = J->beta;
+  const double N = (double)J->N;
+  ee_result* res = J->result;
+  double* scratch = reinterpret_cast<double*>(J->work + n);  // n doubles after the works
+
+  long long mx = LLONG_MIN, mn = LLONG_MAX, sm = 0;
+  for (int i = tid; i < n; i += kEstThreads) {
+    const long long v = I[i];
+    mx = v > mx ? v : mx;
+    mn = v < mn ? v : mn;
+    sm += v;
+  }
+  const long long imax = block_reduce(mx, shl, [](long long a, long long b) { return a > b ? a : b; });
+  const long long imin = block_reduce(mn, shl, [](long long a, long long b) { return a < b ? a : b; });
+  const long long isum = block_reduce(sm, shl, [](long long a, long long b) { return a + b; });
+
+  // contiguous chunks: thread t owns [t*C, min(n, (t+1)*C))
+  const int C = (n + kEstThreads - 1) / kEstThreads;
+  const int lo = min(n, tid * C), hi = min(n, lo + C);
+  double cs = 0.0, cs2 = 0.0;
+  for (int i = lo; i < hi; ++i) {
+    const double e = exp((beta * (double)(I[i] - imax)) / N);
+    scratch[i] = cs;  // prefix within the chunk
+    cs += e;
+    cs2 += e * e;
+  }
+  const double s = block_reduce(cs, shd, [](double a, double b) { return a + b; });
+  const double s2 = block_reduce(cs2, shd, [](double a, double b) { return a + b; });
+  // exclusive prefix / suffix of the chunk sums (serial over 256 values)
+  shd[tid] = cs;
+  __syncthreads();
+  if (tid == 0) {
+    pre[0] = 0.0;
+    for (int k = 0; k < kEstThreads; ++k) pre[k + 1] = pre[k] + shd[k];
+    suf[kEstThreads] = 0.0;
+    for (int k = kEstThreads - 1; k >= 0; --k) suf[k] = suf[k + 1] + shd[k];
+  }
+  __syncthreads();
+  const double shift = (beta * (double)imax) / N;
+  const double dF = -(shift + log(s) - log((double)n));
+  double loo_sum = 0.0;
+  if (n >= 2) {
+    double after = suf[tid + 1];  // sum over later chunks
+    for (int i = hi - 1; i >= lo; --i) {
+      const double e = exp((beta * (double)(I[i] - imax)) / N);
+      const double si = (pre[tid] + scratch[i]) + after;  // sum over j != i
+      after += e;
+      const double loo = -(shift + log(si) - log((double)(n - 1)));
+      scratch[i] = loo;
+      loo_sum += loo;
+    }
+  }
+  const double loo_mean = block_reduce(loo_sum, shd, [](double a, double b) { return a + b; }) / n;
+  const double wscale = beta / N;
+  const double wmean = -wscale * ((double)isum / (double)n);
+  double dev = 0.0, wdev = 0.0;
+  for (int i = lo; i < hi; ++i) {
+    if (n >= 2) {
+      const double d = scratch[i] - loo_mean;
+      dev += d * d;
+    }
+    const double wd = -wscale * (double)I[i] - wmean;
+    wdev += wd * wd;
+  }
+  const double dev_sum = block_reduce(dev, shd, [](double a, double b) { return a + b; });
+  const double wvar = block_reduce(wdev, shd, [](double a, double b) { return a + b; }) / n;
+  if (tid == 0) {
+    res->dF = dF;
+    res->dS = dF / (double)(J->n - 1);
+    res->dF_err = (n >= 2) ? sqrt((double)(n - 1) / (double)n * dev_sum) : __builtin_nan("");
+    res->w_mean = wmean;
+    res->w_var = wvar;
+    res->ess = s * s / s2;
+    res->i_min = imin;
+    res->i_max = imax;
+    res->n_traj = n;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ee_k_max_lds_bytes() { return 160 * 1024 - 256; }
+
+static hipError_t set_lds_attr(const void* fn) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, ee_k_max_lds_bytes());
+}
+
+int ee_k_sweep_kernel_ptr(int /*dim*/, const void** fn) {
+  *fn = reinterpret_cast<const void*>(&sweep_kernel);
+  return (int)set_lds_attr(*fn);
+}
+int ee_k_queue_reset_ptr(const void** fn) {
+  *fn = reinterpret_cast<const void*>(&queue_reset_kernel);
+  return 0;
+}
+int ee_k_estimate_ptr(const void** fn) {
+  *fn = reinterpret_cast<const void*>(&estimate_kernel);
+  return 0;
+}
+
+int ee_k_launch_sweep(int dim, const ee::JobDev* single_job, int single_k, const ee::Unit* units,
+                      int n_units, int* queue, const ee::JobDev* const* jobtab, uint32_t flags,
+                      int n_therm, int g0, int grid, int block, int lds_bytes, void* stream) {
+  const void* fn = nullptr;
+  hipError_t e = (hipError_t)ee_k_sweep_kernel_ptr(dim, &fn);
+  if (e != hipSuccess) return (int)e;
+  (void)dim;
+  hipLaunchKernelGGL(sweep_kernel, dim3(grid), dim3(block), lds_bytes, (hipStream_t)stream, single_job,
+                     single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
+  return (int)hipGetLastError();
+}
+
+int ee_k_launch_queue_reset(int* queue, void* stream) {
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, queue);
+  return (int)hipGetLastError();
+}
+
+int ee_k_launch_estimate(const ee::JobDev* const* jobtab, int count, void* stream) {
+  hipLaunchKernelGGL(estimate_kernel, dim3(count), dim3(kEstThreads), 0, (hipStream_t)stream, jobtab);
+  return (int)hipGetLastError();
+}
+
+}  // extern "C"

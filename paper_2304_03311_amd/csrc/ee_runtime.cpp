@@ -1,0 +1,685 @@
+// ee_runtime.cpp -- host runtime of the C ABI declared in include/ee.h.
+//
+// Validates job descriptions, builds the geometry constants and the uint32
+// Metropolis threshold tables on the host (FP64 libm exp; compiled with
+// -ffp-contract=off so the expression is evaluated exactly as written),
+// lays the job out in the caller's arena, runs the job state machine and
+// launches the kernels of ee_kernels.hip.  The batch path keeps a plan per
+// job set (device work queue + job table + a HIP graph of the launches).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ee_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+ee_status fail(ee_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(EE_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                  __LINE__);                                                            \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+enum State { CREATED = 0, DONE = 2 };
+
+struct Layout {
+  size_t off_jobdev, off_selfptr, off_result, off_ramp, off_work, off_spins, total;
+  int H, G, R, traj_words, packed_words;
+  size_t storage_words_per_traj;
+};
+
+// Metropolis threshold of an energy cost K (units of beta/N): accept iff
+// u <= U with u a uint32 uniform, so P(accept) = (U+1)/2^32 ~ exp(-2 beta K/N).
+uint32_t threshold(double beta, int64_t K, int32_t N) {
+  if (beta * (double)K <= 0.0) return 0xFFFFFFFFu;
+  const double x = (2.0 * beta * (double)K) / (double)N;
+  const double p = std::exp(-x);
+  double f = std::floor(std::ldexp(p, 32));
+  if (f >= 4294967296.0) return 0xFFFFFFFFu;
+  if (f < 1.0) f = 1.0;
+  return (uint32_t)(f - 1.0);
+}
+
+ee_status validate(const ee_job_desc* d) {
+  if (!d) return fail(EE_EINVAL, "desc is NULL");
+  if (d->dim != 2 && d->dim != 3) return fail(EE_EINVAL, "dim must be 2 or 3 (got %d)", d->dim);
+  if (d->lt < 2 || (d->lt & 1)) return fail(EE_EINVAL, "lt must be even and >= 2 (got %d)", d->lt);
+  if (d->lx < 2 || (d->lx & 1)) return fail(EE_EINVAL, "lx must be even and >= 2 (got %d)", d->lx);
+  if (d->dim == 2 && d->ly != 1) return fail(EE_EINVAL, "ly must be 1 in 2D (got %d)", d->ly);
+  if (d->dim == 3 && (d->ly < 2 || (d->ly & 1)))
+    return fail(EE_EINVAL, "ly must be even and >= 2 in 3D (got %d)", d->ly);
+  if (d->n_replicas < 2 || d->n_replicas > (1 << 20))
+    return fail(EE_EINVAL, "n_replicas must be in [2, 2^20] (got %d)", d->n_replicas);
+  if (!(d->beta >= 0.0) || !std::isfinite(d->beta))
+    return fail(EE_EINVAL, "beta must be finite and >= 0");
+  if (d->l < 0 || d->l >= d->lx) return fail(EE_EINVAL, "l must satisfy 0 <= l < lx (got %d)", d->l);
+  if (d->n_step < 1) return fail(EE_EINVAL, "n_step must be >= 1 (got %d)", d->n_step);
+  if (d->n_traj < 1 || d->n_traj > 65535)
+    return fail(EE_EINVAL, "n_traj must be in [1, 65535] (got %d)", d->n_traj);
+  if (d->spin_format != EE_SPINS_INT8 && d->spin_format != EE_SPINS_BITPACKED)
+    return fail(EE_EINVAL, "unknown spin_format %d", d->spin_format);
+  if (d->flags & ~EE_FLAG_REVERSE) return fail(EE_EINVAL, "unknown flags 0x%x", d->flags);
+  // |I| <= 2 n ly N must fit the int32 accumulators
+  if (2.0 * d->n_replicas * d->ly * (double)d->n_step >= 2147483647.0)
+    return fail(EE_EINVAL, "2*n*ly*n_step exceeds the int32 work range");
+  if ((double)d->lt * d->ly * d->lx > 1e8) return fail(EE_EINVAL, "lattice too large");
+  return EE_OK;
+}
+
+Layout layout_of(const ee_job_desc* d) {
+  Layout L{};
+  L.H = d->lx / 2;
+  L.G = (L.H + 3) / 4;
+  L.R = d->lt * d->ly;
+  L.traj_words = 2 * d->n_replicas * L.R * L.G;
+  L.packed_words = 2 * d->n_replicas * L.R * ((L.H + 31) / 32);
+  L.storage_words_per_traj =
+      (d->spin_format == EE_SPINS_INT8) ? (size_t)L.traj_words : (size_t)L.packed_words;
+  size_t off = 0;
+  L.off_jobdev = off; off = align_up(off + sizeof(ee::JobDev));
+  L.off_selfptr = off; off = align_up(off + sizeof(void*));
+  L.off_result = off; off = align_up(off + sizeof(ee_result));
+  L.off_ramp = off; off = align_up(off + (size_t)(d->n_step + 1) * 8 * d->dim * sizeof(uint32_t));
+  L.off_work = off; off = align_up(off + 2 * (size_t)d->n_traj * sizeof(int64_t));  // I_j + estimator scratch
+  L.off_spins = off; off = align_up(off + (size_t)d->n_traj * L.storage_words_per_traj * 4);
+  L.total = off;
+  return L;
+}
+
+struct DeviceInfo {
+  int cus = 0;
+  int max_lds = 0;
+};
+
+DeviceInfo device_info() {
+  static std::mutex mu;
+  static std::vector<DeviceInfo> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1);
+  if (cache[dev].cus == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) cache[dev].cus = v;
+    if (cache[dev].cus <= 0) cache[dev].cus = 256;
+    cache[dev].max_lds = ee_k_max_lds_bytes();
+  }
+  return cache[dev];
+}
+
+constexpr int kDefaultBlock = 1024;
+constexpr int kDefaultLdsBudget = 80 * 1024;  // two workgroups per CU
+
+// Trajectories per workgroup that maximise the trajectories finished per
+// unit of workgroup time, within the LDS budget.
+int choose_slots(const Layout& L, int n_rep, int block, int lds_budget, int n_traj) {
+  const int traj_bytes = L.traj_words * 4;
+  int kmax = std::min(ee::kMaxSlots, std::max(1, lds_budget / traj_bytes));
+  kmax = std::min(kmax, std::max(1, block / L.G));
+  kmax = std::min(kmax, std::max(1, n_traj));
+  const int nrows = n_rep * L.R;
+  int best_k = 1;
+  double best = -1.0;
+  for (int k = 1; k <= kmax; ++k) {
+    const int T = block / k;
+    const int nrg = T / L.G;
+    if (nrg < 1) break;
+    const int iters = (nrows + nrg - 1) / nrg;
+    const double rate = (double)k / iters;
+    if (rate > best * 1.0001) {
+      best = rate;
+      best_k = k;
+    }
+  }
+  return best_k;
+}
+
+}  // namespace
+
+struct ee_job {
+  ee_job_desc d;
+  Layout L;
+  hipStream_t stream;
+  uint8_t* arena;
+  size_t arena_bytes;
+  ee::JobDev host_jobdev;  // kept alive for the asynchronous upload
+  const ee::JobDev* host_selfptr;
+  std::vector<uint32_t> host_ramp;
+  int state;
+  bool spins_exist;
+  int64_t g;
+  int64_t n_therm_total;
+  bool est_enqueued;
+  hipStream_t est_stream;
+  ee_launch_cfg cfg;
+  ee::JobDev* dev_jobdev() const { return reinterpret_cast<ee::JobDev*>(arena + L.off_jobdev); }
+  const ee::JobDev* const* dev_selfptr() const {
+    return reinterpret_cast<const ee::JobDev* const*>(arena + L.off_selfptr);
+  }
+  ee_result* dev_result() const { return reinterpret_cast<ee_result*>(arena + L.off_result); }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Batch plans: device queue + job table + units, and a HIP graph of
+// [queue reset] -> [event] -> [persistent sweep kernel] -> [event] -> [estimator]
+// ---------------------------------------------------------------------------
+struct Plan {
+  std::vector<ee_job*> jobs;
+  int n_therm = 0;
+  ee_launch_cfg cfg{};
+  int dim = 0;
+  int block = 0, lds = 0, grid = 0, n_units = 0;
+  void* dev_buf = nullptr;
+  int* dev_queue = nullptr;
+  const ee::JobDev** dev_jobtab = nullptr;
+  ee::Unit* dev_units = nullptr;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~Plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev_start) (void)hipEventDestroy(ev_start);
+    if (ev_stop) (void)hipEventDestroy(ev_stop);
+    if (dev_buf) (void)hipFree(dev_buf);
+  }
+};
+
+std::mutex g_plan_mu;
+std::list<Plan*> g_plans;  // most recent first
+constexpr size_t kMaxPlans = 16;
+thread_local Plan* g_last_plan = nullptr;
+
+void drop_plans_with(ee_job* j) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  for (auto it = g_plans.begin(); it != g_plans.end();) {
+    Plan* p = *it;
+    if (std::find(p->jobs.begin(), p->jobs.end(), j) != p->jobs.end()) {
+      if (g_last_plan == p) g_last_plan = nullptr;
+      (void)hipDeviceSynchronize();
+      delete p;
+      it = g_plans.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+bool same_cfg(const ee_launch_cfg& a, const ee_launch_cfg& b) {
+  return a.block_threads == b.block_threads && a.lds_bytes == b.lds_bytes &&
+         a.grid_blocks == b.grid_blocks && a.use_graph == b.use_graph;
+}
+
+ee_status launch_sweep_for_job(ee_job* j, uint32_t flags, int n_therm) {
+  const int block = j->cfg.block_threads > 0 ? j->cfg.block_threads : kDefaultBlock;
+  const int budget = j->cfg.lds_bytes > 0 ? j->cfg.lds_bytes : kDefaultLdsBudget;
+  const int k = choose_slots(j->L, j->d.n_replicas, block, std::max(budget, j->L.traj_words * 4), j->d.n_traj);
+  const int grid = (j->d.n_traj + k - 1) / k;
+  const int lds = k * j->L.traj_words * 4;
+  const int rc = ee_k_launch_sweep(j->d.dim, j->dev_jobdev(), k, nullptr, 0, nullptr, nullptr, flags,
+                                   n_therm, (int)j->g, grid, block, lds, j->stream);
+  if (rc != 0) return fail(EE_EHIP, "sweep kernel launch failed: %s", hipGetErrorString((hipError_t)rc));
+  return EE_OK;
+}
+
+ee_status check_cfg(const ee_launch_cfg* cfg) {
+  if (!cfg) return EE_OK;
+  if (cfg->block_threads != 0 &&
+      (cfg->block_threads < 64 || cfg->block_threads > 1024 || (cfg->block_threads % 64)))
+    return fail(EE_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
+  if (cfg->lds_bytes < 0 || cfg->lds_bytes > ee_k_max_lds_bytes())
+    return fail(EE_EINVAL, "lds_bytes must be in [0, %d]", ee_k_max_lds_bytes());
+  if (cfg->grid_blocks < 0) return fail(EE_EINVAL, "grid_blocks must be >= 0");
+  return EE_OK;
+}
+
+ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launch_cfg& cfg,
+                     hipStream_t stream, Plan** out) {
+  auto P = new Plan();
+  P->jobs.assign(jobs, jobs + count);
+  P->n_therm = n_therm;
+  P->cfg = cfg;
+  P->dim = jobs[0]->d.dim;
+  P->block = cfg.block_threads > 0 ? cfg.block_threads : kDefaultBlock;
+  int budget = cfg.lds_bytes > 0 ? cfg.lds_bytes : kDefaultLdsBudget;
+  for (int i = 0; i < count; ++i) budget = std::max(budget, jobs[i]->L.traj_words * 4);
+  // units: per job, blocks of k trajectories; longest first
+  struct U { ee::Unit u; double cost; };
+  std::vector<U> units;
+  int lds_need = 0;
+  for (int i = 0; i < count; ++i) {
+    ee_job* j = jobs[i];
+    const int k = choose_slots(j->L, j->d.n_replicas, P->block, budget, j->d.n_traj);
+    lds_need = std::max(lds_need, k * j->L.traj_words * 4);
+    const int T = P->block / k;
+    const int nrg = std::max(1, T / j->L.G);
+    const double iters = std::ceil((double)j->d.n_replicas * j->L.R / nrg);
+    const double cost = iters * (double)(n_therm + j->d.n_step);
+    for (int j0 = 0; j0 < j->d.n_traj; j0 += k)
+      units.push_back({ee::Unit{i, j0, std::min(k, j->d.n_traj - j0), k}, cost});
+  }
+  std::stable_sort(units.begin(), units.end(), [](const U& a, const U& b) { return a.cost > b.cost; });
+  P->lds = lds_need;
+  P->n_units = (int)units.size();
+  // persistent grid: as many workgroups as fit on the GPU at once
+  const void* fn = nullptr;
+  int rc = ee_k_sweep_kernel_ptr(P->dim, &fn);
+  if (rc != 0) { delete P; return fail(EE_EHIP, "kernel attribute: %s", hipGetErrorString((hipError_t)rc)); }
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, P->block, P->lds);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  const DeviceInfo di = device_info();
+  P->grid = cfg.grid_blocks > 0 ? cfg.grid_blocks : di.cus * per_cu;
+  P->grid = std::max(1, std::min(P->grid, P->n_units));
+  // device metadata
+  const size_t off_tab = kAlign;
+  const size_t off_units = align_up(off_tab + sizeof(void*) * count);
+  const size_t bytes = off_units + sizeof(ee::Unit) * units.size();
+  e = hipMalloc(&P->dev_buf, bytes);
+  if (e != hipSuccess) { delete P; return fail(EE_EHIP, "hipMalloc(batch plan): %s", hipGetErrorString(e)); }
+  P->dev_queue = reinterpret_cast<int*>(P->dev_buf);
+  P->dev_jobtab = reinterpret_cast<const ee::JobDev**>((uint8_t*)P->dev_buf + off_tab);
+  P->dev_units = reinterpret_cast<ee::Unit*>((uint8_t*)P->dev_buf + off_units);
+  std::vector<uint8_t> host(bytes, 0);
+  for (int i = 0; i < count; ++i)
+    reinterpret_cast<const ee::JobDev**>(host.data() + off_tab)[i] = jobs[i]->dev_jobdev();
+  for (size_t i = 0; i < units.size(); ++i)
+    reinterpret_cast<ee::Unit*>(host.data() + off_units)[i] = units[i].u;
+  e = hipMemcpy(P->dev_buf, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { delete P; return fail(EE_EHIP, "upload of batch plan: %s", hipGetErrorString(e)); }
+  if (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess) {
+    delete P;
+    return fail(EE_EHIP, "hipEventCreate failed");
+  }
+  if (cfg.use_graph) {
+    hipGraph_t g;
+    e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) { delete P; return fail(EE_EHIP, "hipGraphCreate: %s", hipGetErrorString(e)); }
+    P->graph = g;
+    const void* f_reset = nullptr;
+    const void* f_est = nullptr;
+    ee_k_queue_reset_ptr(&f_reset);
+    ee_k_estimate_ptr(&f_est);
+    hipGraphNode_t n_reset, n_ev0, n_sweep, n_ev1, n_est;
+    int* q = P->dev_queue;
+    void* a_reset[] = {&q};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(f_reset);
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = a_reset;
+    e = hipGraphAddKernelNode(&n_reset, g, nullptr, 0, &kp);
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&n_ev0, g, &n_reset, 1, P->ev_start);
+    const ee::JobDev* sj = nullptr;
+    int sk = 0;
+    const ee::Unit* un = P->dev_units;
+    int nu = P->n_units;
+    const ee::JobDev* const* jt = P->dev_jobtab;
+    uint32_t fl = ee::kFlagInit | ee::kFlagProto;
+    int nt = n_therm, g0 = 0;
+    void* a_sweep[] = {&sj, &sk, &un, &nu, &q, &jt, &fl, &nt, &g0};
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = dim3(P->grid);
+    kp.blockDim = dim3(P->block);
+    kp.sharedMemBytes = P->lds;
+    kp.kernelParams = a_sweep;
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&n_sweep, g, &n_ev0, 1, &kp);
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&n_ev1, g, &n_sweep, 1, P->ev_stop);
+    void* a_est[] = {&jt};
+    kp.func = const_cast<void*>(f_est);
+    kp.gridDim = dim3(count);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = a_est;
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&n_est, g, &n_ev1, 1, &kp);
+    if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { delete P; return fail(EE_EHIP, "building the batch graph: %s", hipGetErrorString(e)); }
+  }
+  (void)stream;
+  *out = P;
+  return EE_OK;
+}
+
+ee_status run_plan(Plan* P, hipStream_t stream) {
+  if (P->exec) {
+    HIP_TRY(hipGraphLaunch(P->exec, stream));
+  } else {
+    int rc = ee_k_launch_queue_reset(P->dev_queue, stream);
+    if (rc) return fail(EE_EHIP, "queue reset launch: %s", hipGetErrorString((hipError_t)rc));
+    HIP_TRY(hipEventRecord(P->ev_start, stream));
+    rc = ee_k_launch_sweep(P->dim, nullptr, 0, P->dev_units, P->n_units, P->dev_queue, P->dev_jobtab,
+                           ee::kFlagInit | ee::kFlagProto, P->n_therm, 0, P->grid, P->block, P->lds, stream);
+    if (rc) return fail(EE_EHIP, "persistent sweep launch: %s", hipGetErrorString((hipError_t)rc));
+    HIP_TRY(hipEventRecord(P->ev_stop, stream));
+    rc = ee_k_launch_estimate(P->dev_jobtab, (int)P->jobs.size(), stream);
+    if (rc) return fail(EE_EHIP, "estimator launch: %s", hipGetErrorString((hipError_t)rc));
+  }
+  return EE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ee_last_error(void) { return g_err.c_str(); }
+const char* ee_version(void) { return "ee-mi355x 0.1 (gfx950)"; }
+
+ee_status ee_job_footprint(const ee_job_desc* desc, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(EE_EINVAL, "bytes is NULL");
+  ee_status s = validate(desc);
+  if (s) return s;
+  Layout L = layout_of(desc);
+  if (L.traj_words * 4 > ee_k_max_lds_bytes())
+    return fail(EE_EUNSUPPORTED, "one trajectory needs %d bytes of LDS (max %d)", L.traj_words * 4,
+                ee_k_max_lds_bytes());
+  *bytes = L.total;
+  return EE_OK;
+}
+
+ee_status ee_job_create(const ee_job_desc* desc, void* dev_arena, size_t arena_bytes, void* hip_stream,
+                        ee_job** out) {
+  g_err.clear();
+  if (!out) return fail(EE_EINVAL, "out is NULL");
+  size_t need = 0;
+  ee_status s = ee_job_footprint(desc, &need);
+  if (s) return s;
+  if (!dev_arena) return fail(EE_EINVAL, "arena is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_arena) % kAlign) return fail(EE_EINVAL, "arena must be 256-byte aligned");
+  if (arena_bytes < need) return fail(EE_ENOMEM, "arena has %zu bytes, the job needs %zu", arena_bytes, need);
+  ee_job* j = new ee_job();
+  j->d = *desc;
+  j->L = layout_of(desc);
+  j->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  j->arena = reinterpret_cast<uint8_t*>(dev_arena);
+  j->arena_bytes = arena_bytes;
+  j->state = CREATED;
+  j->spins_exist = false;
+  j->g = 0;
+  j->n_therm_total = 0;
+  j->est_enqueued = false;
+  j->est_stream = j->stream;
+  j->cfg = ee_launch_cfg{0, 0, 0, 1};
+  const int dim = desc->dim, N = desc->n_step;
+  // thresholds
+  ee::JobDev& D = j->host_jobdev;
+  std::memset(&D, 0, sizeof(D));
+  D.dim = dim; D.lt = desc->lt; D.lx = desc->lx; D.ly = desc->ly; D.n = desc->n_replicas;
+  D.l = desc->l; D.N = N; D.n_traj = desc->n_traj;
+  D.H = j->L.H; D.G = j->L.G; D.R = j->L.R; D.traj_words = j->L.traj_words;
+  D.packed_words = j->L.packed_words;
+  D.key0 = (uint32_t)(desc->seed & 0xFFFFFFFFu);
+  D.key1 = (uint32_t)(desc->seed >> 32);
+  for (int a = 0; a < dim; ++a) D.thr_bulk[a] = threshold(desc->beta, (int64_t)N * (2 * dim - 2 * a), N);
+  D.reverse = (desc->flags & EE_FLAG_REVERSE) ? 1u : 0u;
+  D.spin_format = (uint32_t)desc->spin_format;
+  ee::Magic mr = ee::make_magic((uint32_t)j->L.R), my = ee::make_magic((uint32_t)desc->ly);
+  D.magic_R = mr.mul; D.shift_R = mr.shift; D.magic_Ly = my.mul; D.shift_Ly = my.shift;
+  D.beta = desc->beta;
+  D.ramp_thr = reinterpret_cast<const uint32_t*>(j->arena + j->L.off_ramp);
+  D.spins = reinterpret_cast<uint32_t*>(j->arena + j->L.off_spins);
+  D.work = reinterpret_cast<int64_t*>(j->arena + j->L.off_work);
+  D.result = j->dev_result();
+  // ramped-site thresholds U_m[fa][b][c], K = N(2dim-1-2fa) + (N-m)(1-2b) + m(1-2c)
+  j->host_ramp.resize((size_t)(N + 1) * 8 * dim);
+  for (int m = 0; m <= N; ++m)
+    for (int fa = 0; fa < 2 * dim; ++fa)
+      for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c) {
+          const int64_t K = (int64_t)N * (2 * dim - 1 - 2 * fa) + (int64_t)(N - m) * (1 - 2 * b) +
+                            (int64_t)m * (1 - 2 * c);
+          j->host_ramp[(size_t)m * 8 * dim + fa * 4 + b * 2 + c] = threshold(desc->beta, K, N);
+        }
+  j->host_selfptr = j->dev_jobdev();
+  hipError_t e = hipMemcpyAsync(j->dev_jobdev(), &j->host_jobdev, sizeof(ee::JobDev), hipMemcpyHostToDevice, j->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(j->arena + j->L.off_selfptr, &j->host_selfptr, sizeof(void*), hipMemcpyHostToDevice, j->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(j->arena + j->L.off_ramp, j->host_ramp.data(), j->host_ramp.size() * 4,
+                       hipMemcpyHostToDevice, j->stream);
+  if (e != hipSuccess) {
+    delete j;
+    return fail(EE_EHIP, "upload of job tables: %s", hipGetErrorString(e));
+  }
+  *out = j;
+  return EE_OK;
+}
+
+ee_status ee_job_set_launch(ee_job* job, const ee_launch_cfg* cfg) {
+  g_err.clear();
+  if (!job) return fail(EE_EINVAL, "job is NULL");
+  ee_status s = check_cfg(cfg);
+  if (s) return s;
+  job->cfg = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1};
+  return EE_OK;
+}
+
+ee_status ee_thermalize(ee_job* job, int32_t n_sweeps) {
+  g_err.clear();
+  if (!job) return fail(EE_EINVAL, "job is NULL");
+  if (n_sweeps < 0) return fail(EE_EINVAL, "n_sweeps must be >= 0");
+  if (job->state != CREATED) return fail(EE_ESTATE, "ee_thermalize after the protocol");
+  if (job->g + n_sweeps > 0x7FFFFFFF - (int64_t)job->d.n_step) return fail(EE_EINVAL, "sweep counter overflow");
+  uint32_t flags = job->spins_exist ? 0u : ee::kFlagInit;
+  if (n_sweeps == 0 && job->spins_exist) return EE_OK;
+  ee_status s = launch_sweep_for_job(job, flags, n_sweeps);
+  if (s) return s;
+  job->spins_exist = true;
+  job->g += n_sweeps;
+  job->n_therm_total += n_sweeps;
+  return EE_OK;
+}
+
+ee_status ee_run_protocol(ee_job* job) {
+  g_err.clear();
+  if (!job) return fail(EE_EINVAL, "job is NULL");
+  if (job->state != CREATED) return fail(EE_ESTATE, "the protocol runs once per job");
+  if (!job->spins_exist) return fail(EE_ESTATE, "call ee_thermalize (possibly with 0 sweeps) first");
+  ee_status s = launch_sweep_for_job(job, ee::kFlagProto, 0);
+  if (s) return s;
+  job->g += job->d.n_step;
+  job->state = DONE;
+  job->est_enqueued = false;
+  return EE_OK;
+}
+
+ee_status ee_estimate(ee_job* job, ee_result* out) {
+  g_err.clear();
+  if (!job || !out) return fail(EE_EINVAL, "NULL argument");
+  if (job->state != DONE) return fail(EE_ESTATE, "ee_estimate before the protocol");
+  if (!job->est_enqueued) {
+    int rc = ee_k_launch_estimate(job->dev_selfptr(), 1, job->stream);
+    if (rc) return fail(EE_EHIP, "estimator launch: %s", hipGetErrorString((hipError_t)rc));
+    job->est_enqueued = true;
+    job->est_stream = job->stream;
+  }
+  ee_result r;
+  HIP_TRY(hipMemcpyAsync(&r, job->dev_result(), sizeof(r), hipMemcpyDeviceToHost, job->est_stream));
+  HIP_TRY(hipStreamSynchronize(job->est_stream));
+  r.n_traj = job->d.n_traj;
+  r.attempts = (int64_t)job->d.n_traj * job->d.n_replicas * job->d.lt * job->d.ly * job->d.lx *
+               (job->n_therm_total + job->d.n_step);
+  r.reserved = 0;
+  *out = r;
+  return EE_OK;
+}
+
+ee_status ee_job_read_work(ee_job* job, int64_t* host_I, int32_t count) {
+  g_err.clear();
+  if (!job || (!host_I && count > 0)) return fail(EE_EINVAL, "NULL argument");
+  if (job->state != DONE) return fail(EE_ESTATE, "no works before the protocol");
+  if (count < 0 || count > job->d.n_traj) return fail(EE_EINVAL, "count must be in [0, n_traj]");
+  if (count == 0) return EE_OK;
+  HIP_TRY(hipMemcpyAsync(host_I, job->arena + job->L.off_work, sizeof(int64_t) * count,
+                         hipMemcpyDeviceToHost, job->est_stream));
+  HIP_TRY(hipStreamSynchronize(job->est_stream));
+  return EE_OK;
+}
+
+ee_status ee_job_read_spins(ee_job* job, int8_t* host, size_t count) {
+  g_err.clear();
+  if (!job || (!host && count > 0)) return fail(EE_EINVAL, "NULL argument");
+  if (!job->spins_exist) return fail(EE_ESTATE, "no spins before ee_thermalize");
+  const ee_job_desc& d = job->d;
+  const size_t per = (size_t)d.n_replicas * d.lt * d.ly * d.lx;
+  if (count % per || count / per > (size_t)d.n_traj)
+    return fail(EE_EINVAL, "count must be a multiple of %zu and at most n_traj of them", per);
+  const size_t nt = count / per;
+  if (nt == 0) return EE_OK;
+  const size_t words = job->L.storage_words_per_traj;
+  std::vector<uint32_t> raw(nt * words);
+  HIP_TRY(hipMemcpyAsync(raw.data(), job->arena + job->L.off_spins, raw.size() * 4, hipMemcpyDeviceToHost,
+                         job->est_stream));
+  HIP_TRY(hipStreamSynchronize(job->est_stream));
+  const int n = d.n_replicas, R = job->L.R, G = job->L.G, H = job->L.H;
+  const int PW = (H + 31) / 32;
+  for (size_t j = 0; j < nt; ++j) {
+    const uint32_t* tw = raw.data() + j * words;
+    for (int c = 0; c < 2; ++c)
+      for (int r = 0; r < n; ++r)
+        for (int t = 0; t < d.lt; ++t)
+          for (int y = 0; y < d.ly; ++y) {
+            const int rho = t * d.ly + y;
+            const size_t rowg = ((size_t)c * n + r) * R + rho;
+            for (int h = 0; h < H; ++h) {
+              int bit;
+              if (d.spin_format == EE_SPINS_INT8)
+                bit = (tw[rowg * G + (h >> 2)] >> (8 * (h & 3))) & 1;
+              else
+                bit = (tw[rowg * PW + (h >> 5)] >> (h & 31)) & 1;
+              const int x = 2 * h + ((c + t + y) & 1);
+              host[(((j * n + r) * d.lt + t) * d.ly + y) * d.lx + x] = bit ? 1 : -1;
+            }
+          }
+  }
+  return EE_OK;
+}
+
+ee_status ee_job_reset(ee_job* job) {
+  g_err.clear();
+  if (!job) return fail(EE_EINVAL, "job is NULL");
+  job->state = CREATED;
+  job->spins_exist = false;
+  job->g = 0;
+  job->n_therm_total = 0;
+  job->est_enqueued = false;
+  return EE_OK;
+}
+
+ee_status ee_batch_run_cfg(ee_job* const* jobs, int32_t count, int32_t n_therm, const ee_launch_cfg* cfg,
+                           void* hip_stream) {
+  g_err.clear();
+  if (!jobs || count < 1) return fail(EE_EINVAL, "need at least one job");
+  if (n_therm < 0) return fail(EE_EINVAL, "n_therm must be >= 0");
+  ee_status s = check_cfg(cfg);
+  if (s) return s;
+  ee_launch_cfg c = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1};
+  for (int i = 0; i < count; ++i) {
+    if (!jobs[i]) return fail(EE_EINVAL, "jobs[%d] is NULL", i);
+    if (jobs[i]->state != CREATED || jobs[i]->spins_exist)
+      return fail(EE_ESTATE, "jobs[%d] is not freshly created (use ee_job_reset)", i);
+    for (int k = 0; k < i; ++k)
+      if (jobs[k] == jobs[i]) return fail(EE_EINVAL, "jobs[%d] appears twice", i);
+    if ((int64_t)n_therm + jobs[i]->d.n_step > 0x7FFFFFFF) return fail(EE_EINVAL, "sweep counter overflow");
+  }
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // the job tables must be uploaded before the batch reads them
+  for (int i = 0; i < count; ++i)
+    if (jobs[i]->stream != stream) HIP_TRY(hipStreamSynchronize(jobs[i]->stream));
+  Plan* P = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
+      Plan* q = *it;
+      if (q->n_therm == n_therm && same_cfg(q->cfg, c) && (int)q->jobs.size() == count &&
+          std::equal(q->jobs.begin(), q->jobs.end(), jobs)) {
+        P = q;
+        g_plans.erase(it);
+        g_plans.push_front(P);
+        break;
+      }
+    }
+  }
+  if (!P) {
+    s = build_plan(jobs, count, n_therm, c, stream, &P);
+    if (s) return s;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans.push_front(P);
+    while (g_plans.size() > kMaxPlans) {
+      Plan* old = g_plans.back();
+      g_plans.pop_back();
+      if (g_last_plan == old) g_last_plan = nullptr;
+      (void)hipDeviceSynchronize();
+      delete old;
+    }
+  }
+  s = run_plan(P, stream);
+  if (s) return s;
+  g_last_plan = P;
+  for (int i = 0; i < count; ++i) {
+    ee_job* j = jobs[i];
+    j->spins_exist = true;
+    j->g = (int64_t)n_therm + j->d.n_step;
+    j->n_therm_total = n_therm;
+    j->state = DONE;
+    j->est_enqueued = true;
+    j->est_stream = stream;
+  }
+  return EE_OK;
+}
+
+ee_status ee_batch_run(ee_job* const* jobs, int32_t count, int32_t n_therm, void* hip_stream) {
+  return ee_batch_run_cfg(jobs, count, n_therm, nullptr, hip_stream);
+}
+
+ee_status ee_batch_kernel_ms(double* ms) {
+  g_err.clear();
+  if (!ms) return fail(EE_EINVAL, "ms is NULL");
+  Plan* P = g_last_plan;
+  if (!P) return fail(EE_ESTATE, "no batch has run on this thread");
+  HIP_TRY(hipEventSynchronize(P->ev_stop));
+  float f = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&f, P->ev_start, P->ev_stop));
+  *ms = (double)f;
+  return EE_OK;
+}
+
+ee_status ee_job_destroy(ee_job* job) {
+  g_err.clear();
+  if (!job) return EE_OK;
+  drop_plans_with(job);
+  (void)hipStreamSynchronize(job->stream);
+  if (job->est_stream != job->stream) (void)hipStreamSynchronize(job->est_stream);
+  delete job;
+  return EE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+"""Seeded synthetic job sets of the benchmark configurations.
+
+This module holds only problem statements (lattice shapes, couplings,
+protocol lengths, seeds, arrival times); none of the estimator's
+arithmetic.  The GPU path and the CPU oracle receive the same job lists.
+
+Configurations (the paper's own runs use L_tau = 8L in 2D and 4L in 3D,
+Sec. 4 and Sec. 5; the benchmark shapes below read L_tau = L literally):
+  1. 2D 16x16, n = 2, beta_c, l = 4 -> 5, N = 256, 100 thermalisation
+     sweeps, 64 trajectories, int8, seed 1.
+  2. 2D 64x64, n = 2, beta_c, l = 0..63 (64 jobs, S_2(1..64)), N = 1000,
+     1024 trajectories per job, int8, seeds 1 + l.
+  3. 3D 32^3, n = 2, beta = 0.2216546, l = 8, N = 2000, 512 trajectories,
+     bit-packed, seed 1.
+  4. 24 uneven jobs: 2D L in {24,32,48,64,96} and 3D L in {16,24,32}, each
+     with N in {500,1000,2000}; L_tau = L, beta = beta_c of the dimension,
+     l uniform in [0, L) from a PCG64 stream (seed 1), 256 trajectories,
+     2D int8 and 3D bit-packed, seeds 1 + index.
+  5. serving stream: see ``serving_stream``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .ee import EE_SPINS_BITPACKED, EE_SPINS_INT8, JobSpec
+
+BETA_C_2D = 0.5 * math.log(1.0 + math.sqrt(2.0))  # Sec. 4
+BETA_3D = 0.2216546                                 # Sec. 5 (beta_c = 0.221654626(5))
+N_THERM = 100
+
+# launch shape the benchmark times (None = library defaults)
+BENCH_LAUNCH = None
+
+
+def config1_job() -> JobSpec:
+    return JobSpec(dim=2, lt=16, lx=16, ly=1, n=2, beta=BETA_C_2D, l=4, n_step=256, n_traj=64, seed=1)
+
+
+def config2_jobs(L: int = 64, n_step: int = 1000, n_traj: int = 1024, lt: int | None = None) -> list[JobSpec]:
+    lt = L if lt is None else lt
+    return [JobSpec(dim=2, lt=lt, lx=L, ly=1, n=2, beta=BETA_C_2D, l=l, n_step=n_step, n_traj=n_traj,
+                    seed=1 + l) for l in range(L)]
+
+
+def config3_job(spin_format: int = EE_SPINS_BITPACKED) -> JobSpec:
+    return JobSpec(dim=3, lt=32, lx=32, ly=32, n=2, beta=BETA_3D, l=8, n_step=2000, n_traj=512, seed=1,
+                   spin_format=spin_format)
+
+
+def config4_jobs(n_traj: int = 256) -> list[JobSpec]:
+    rng = np.random.Generator(np.random.PCG64(1))
+    shapes = [(2, L) for L in (24, 32, 48, 64, 96)] + [(3, L) for L in (16, 24, 32)]
+    out = []
+    idx = 0
+    for dim, L in shapes:
+        for n_step in (500, 1000, 2000):
+            l = int(rng.integers(0, L))
+            out.append(JobSpec(dim=dim, lt=L, lx=L, ly=L if dim == 3 else 1, n=2,
+                               beta=BETA_C_2D if dim == 2 else BETA_3D, l=l, n_step=n_step, n_traj=n_traj,
+                               seed=1 + idx, spin_format=EE_SPINS_INT8 if dim == 2 else EE_SPINS_BITPACKED))
+            idx += 1
+    return out
+
+
+def serving_stream(n_jobs: int, rate_per_s: float, seed: int = 1, max_l3: int = 40,
+                   n_traj_choices=(64, 128, 256, 512), n_step_choices=(500, 1000, 2000)):
+    """Poisson arrivals (mean rate_per_s) of jobs of random dimension, size,
+    beta, l, N and n_t.  Returns [(arrival_time_s, JobSpec)].
+
+    Sizes: 2D L in {24, 32, 48, 64, 96}; 3D L in {16, 24, 32, max_l3}
+    (lattices held on chip); beta in {0.21, 0.2216546, 0.23}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for i in range(n_jobs):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        dim = int(rng.integers(2, 4))
+        if dim == 2:
+            L = int(rng.choice([24, 32, 48, 64, 96]))
+        else:
+            L = int(rng.choice([16, 24, 32, max_l3]))
+        beta = float(rng.choice([0.21, BETA_3D, 0.23]))
+        l = int(rng.integers(0, L))
+        n_step = int(rng.choice(n_step_choices))
+        n_traj = int(rng.choice(n_traj_choices))
+        out.append((t, JobSpec(dim=dim, lt=L, lx=L, ly=L if dim == 3 else 1, n=2, beta=beta, l=l,
+                               n_step=n_step, n_traj=n_traj, seed=1000 + i,
+                               spin_format=EE_SPINS_INT8 if dim == 2 else EE_SPINS_BITPACKED)))
+    return out
