@@ -39,18 +39,15 @@ def kernel_hash() -> str:
 
 
 def ops_per_attempt(dim: int) -> float:
-    """Algorithmic 32-bit integer VALU operations per Metropolis attempt.
+    """Algorithmic VALU lane-instructions per Metropolis attempt on gfx950.
 
-    A quarter of one Philox4x32-10 call (10 rounds of 2 multiply-high, 2
-    multiply-low and 4 xor = 80 ops per call, 4 uniforms) = 20, plus the
-    update of 4 same-colour sites sharing one 32-bit word: 2*dim xor and
-    2*dim-1 add for the anti-aligned counts (shared by 4 sites), and per site
-    byte extract, threshold select (dim compares+selects), compare, flip-bit
-    insert.  See the roofline section of the design notes."""
-    philox = 80.0 / 4.0
-    counts = (2 * dim + 2 * dim - 1) / 4.0
-    per_site = 1 + 2 * dim + 1 + 2
-    return philox + counts + per_site
+    The minimal instruction sequence of the method: a quarter of one
+    Philox4x32-10 call (10 rounds of 2 v_mad_u64_u32 and 2 three-input xor =
+    40 per call, 4 uniforms) = 10, plus, per 32-bit word of 4 same-colour
+    sites, 2*dim xor-add of the anti-aligned neighbour counts, 1 byte-align
+    for the x neighbours, 3 per site for the acceptance (extract, compare,
+    select) and 1 xor to apply the flips."""
+    return 10.0 + (2 * dim + 1 + 3 * 4 + 1) / 4.0
 
 
 def cpu_baseline(n_traj_sample: int) -> dict:
@@ -75,6 +72,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32, help="oracle trajectories timed for cpu_baseline")
     ap.add_argument("--per-job", action="store_true", help="also time the per-job launch path")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the run, copy 256 MiB device-to-device once (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build runs on one GPU "
@@ -134,7 +133,8 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8 spins, uint32 RNG/thresholds, int32 work, fp64 estimator",
+        "dtype": "int8",
+        "dtype_note": "int8 spins, uint32 uniforms and thresholds (integer compare), int32 work, fp64 estimator",
         "data": "synthetic (seeded job descriptions; spins and uniforms drawn on device)",
         "config": {"workload": "2D Ising 64x64, n=2, beta_c, l=0..63 (64 jobs), N=1000, "
                                "N_therm=100, n_t=1024, int8, persistent batched path",
@@ -163,6 +163,13 @@ def main() -> int:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     for j in jobs:
         j.close()
+    if args.calib_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel() * 4
     print(json.dumps(out), flush=True)
     return 0
 

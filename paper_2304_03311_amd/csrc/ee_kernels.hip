@@ -1,7 +1,7 @@
 // ee_kernels.hip -- gfx950 kernels of the non-equilibrium Renyi-entropy
 // estimator (Bulgarelli & Panero, arXiv:2304.03311).
 //
-// sweep_kernel<DIM>: one workgroup holds k trajectories of one job in LDS
+// sweep_kernel: one workgroup holds k trajectories of one job in LDS
 //   (int8 spins, colour-separated rows) and runs, entirely on chip, the
 //   initial spins, the thermalisation sweeps and the N protocol sweeps with
 //   the integer work (Sec. 3 linear protocol; App. A work-then-update).
@@ -36,15 +36,20 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mul, uint32_t shif
   return (__umulhi(n, mul) + n) >> shift;
 }
 
-// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products.
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products;
+// the two xors of each output word are one 3-input bitwise op (table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                          uint32_t k0, uint32_t k1, uint32_t out[4]) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -81,109 +86,97 @@ __device__ __forceinline__ JP load_jp(const JobDev* J) {
   return P;
 }
 
-// Accept bits of the 4 bulk/glued sites of a word: a holds the number of
-// anti-aligned neighbours per byte (0..2*DIM).  The energy cost is
-// 2*beta*(2*DIM - 2a); a >= DIM never raises the energy.
-template <int DIM>
-__device__ __forceinline__ uint32_t decide(uint32_t a, const uint32_t u[4], const JP& P) {
-  uint32_t f = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const uint32_t ai = (a >> (8 * i)) & 0xFFu;
-    uint32_t thr;
-    if (DIM == 2) {
-      thr = (ai == 0) ? P.thr0 : ((ai == 1) ? P.thr1 : 0xFFFFFFFFu);
-    } else {
-      thr = (ai == 0) ? P.thr0 : ((ai == 1) ? P.thr1 : ((ai == 2) ? P.thr2 : 0xFFFFFFFFu));
-    }
-    f |= (uint32_t)(u[i] <= thr) << (8 * i);
-  }
-  return f;
-}
+// Per-lane iteration state of one work unit (the same for every sweep):
+// the lane owns word w of rows row0, row0 + nrg, ...; (r0, t0, y0) is the
+// first row decoded and nrg = dr*R + dt*ly + dy the row stride.
+struct Lane {
+  int w, wl, wr;
+  int row0, nrg;
+  int r0, t0, y0;
+  int dr, dt, dy;
+};
 
-// One half-sweep of colour c over the rows of one trajectory owned by this
-// lane (fixed word w, rows rg, rg+nrg, ...).  L: the trajectory in LDS.
-template <int DIM>
-__device__ __forceinline__ void half_sweep(const JP& P, uint32_t* __restrict__ L, const int c,
-                                           const int w, const int rg, const int nrg,
-                                           const uint32_t g, const uint32_t j, const int m,
+__device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) { return (a ^ b) + c; }
+
+// One half-sweep of colour c over the lane's rows of one trajectory.
+//   L    the trajectory in LDS (two colour planes)
+//   thr  LDS table: thr[a] = threshold of a bulk/glued site with a
+//        anti-aligned neighbours (2^32-1 for a >= DIM)
+// FULL: lx/2 is a multiple of 4 (no pad bytes, x-neighbours by byte
+// alignment of two words).  UJ: the trajectory index is uniform per wave.
+template <int DIM, bool FULL, bool UJ>
+__device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t* __restrict__ L,
+                                           const uint32_t* __restrict__ thr, const int c,
+                                           const uint32_t g, uint32_t j, const int m,
                                            const bool work, int& dI) {
-  const int cw = P.n * P.R * P.G;  // words per colour plane
+  if (UJ) j = __builtin_amdgcn_readfirstlane(j);
+  const int G = P.G;
+  const int cw = P.n * P.R * G;  // words per colour plane
   uint32_t* __restrict__ Lc = L + c * cw;
   const uint32_t* __restrict__ Lo = L + (c ^ 1) * cw;
   const int nrows = P.n * P.R;
-  const int G = P.G;
-  const int wl = (w == 0) ? G - 1 : w - 1;
-  const int wr = (w == G - 1) ? 0 : w + 1;
-  const int tailsh = 8 * ((P.H - 1) & 3);
-  const uint32_t valid = (w == G - 1 && tailsh != 24) ? ((1u << (tailsh + 8)) - 1u) : 0xFFFFFFFFu;
-  const uint32_t rshift = (w == G - 1) ? (uint32_t)tailsh : 24u;
+  const int LyG = P.ly * G;
+  const int twrap = (P.lt - 1) * LyG;
+  const int ywrap = (P.ly - 1) * G;
   const uint32_t ctr3 = (1u << 28) | (uint32_t)c;
   const int ramp_w = P.l >> 3;
   const int ramp_p = P.l & 1;
   const int ramp_sh = 8 * ((P.l >> 1) & 3);
-
-  for (int row = rg; row < nrows; row += nrg) {
-    const int r = (int)fdiv((uint32_t)row, P.mR, P.sR);
-    const int rho = row - r * P.R;
-    int t, y;
-    if (DIM == 3) {
-      t = (int)fdiv((uint32_t)rho, P.mLy, P.sLy);
-      y = rho - t * P.ly;
-    } else {
-      t = rho;
-      y = 0;
-    }
+  const int w = ln.w;
+  const int tailsh = 8 * ((P.H - 1) & 3);
+  const uint32_t valid = (!FULL && w == G - 1 && tailsh != 24) ? ((1u << (tailsh + 8)) - 1u) : 0xFFFFFFFFu;
+  const uint32_t rshift = (w == G - 1) ? (uint32_t)tailsh : 24u;
+  int r = ln.r0, t = ln.t0, y = ln.y0;
+  int rowbase = ln.row0 * G;
+  const int step = ln.nrg * G;
+  for (int row = ln.row0; row < nrows; row += ln.nrg, rowbase += step) {
     const int p = (c + t + y) & 1;  // x parity of this row's sites
-    const int rbase = r * P.R;
-    const int rowbase = (rbase + rho) * G;
-    const uint32_t S = Lc[rowbase + w];
-    const uint32_t A = Lo[rowbase + w];
-    uint32_t B;
-    if (p) {  // right neighbours x+1: half-index h+1
-      const uint32_t nb = Lo[rowbase + wr] & 0xFFu;
-      B = (A >> 8) | (nb << rshift);
-    } else {  // left neighbours x-1: half-index h-1
-      const uint32_t pd = Lo[rowbase + wl];
-      const uint32_t pb = (w == 0) ? ((pd >> tailsh) & 0xFFu) : (pd >> 24);
-      B = (A << 8) | pb;
+    uint32_t A, B;
+    if (FULL) {
+      // the sites' x-1 (p = 0) or x+1 (p = 1) neighbours straddle words (w-1, w) or (w, w+1)
+      const uint32_t lo = Lo[rowbase + (p ? w : ln.wl)];
+      const uint32_t hi = Lo[rowbase + (p ? ln.wr : w)];
+      B = __builtin_amdgcn_alignbyte(hi, lo, p ? 1u : 3u);
+      A = p ? lo : hi;
+    } else {
+      A = Lo[rowbase + w];
+      const uint32_t nb = Lo[rowbase + (p ? ln.wr : ln.wl)];
+      const uint32_t Br = (A >> 8) | ((nb & 0xFFu) << rshift);
+      const uint32_t Bl = (A << 8) | ((w == 0) ? ((nb >> tailsh) & 0xFFu) : (nb >> 24));
+      B = p ? Br : Bl;
     }
-    const int tm = (t == 0) ? P.lt - 1 : t - 1;
-    const int tp = (t == P.lt - 1) ? 0 : t + 1;
-    const uint32_t Tm = Lo[(rbase + tm * P.ly + y) * G + w];
-    const uint32_t Tp = Lo[(rbase + tp * P.ly + y) * G + w];
-    uint32_t afix = (A ^ S) + (B ^ S);
+    const uint32_t S = Lc[rowbase + w];
+    const uint32_t Tm = Lo[rowbase + ((t == 0) ? twrap : -LyG) + w];
+    const uint32_t Tp = Lo[rowbase + ((t == P.lt - 1) ? -twrap : LyG) + w];
+    uint32_t a = xad(A, S, xad(B, S, xad(Tm, S, Tp ^ S)));
     if (DIM == 3) {
-      const int ym = (y == 0) ? P.ly - 1 : y - 1;
-      const int yp = (y == P.ly - 1) ? 0 : y + 1;
-      afix += (Lo[(rbase + t * P.ly + ym) * G + w] ^ S) + (Lo[(rbase + t * P.ly + yp) * G + w] ^ S);
+      const uint32_t Ym = Lo[rowbase + ((y == 0) ? ywrap : -G) + w];
+      const uint32_t Yp = Lo[rowbase + ((y == P.ly - 1) ? -ywrap : G) + w];
+      a = xad(Ym, S, xad(Yp, S, a));
     }
     uint32_t u[4];
-    philox10((uint32_t)(rho * G + w), g, j, ctr3 | ((uint32_t)r << 1), P.key0, P.key1, u);
-    uint32_t flip;
-    if (t > 1) {
-      flip = decide<DIM>(afix + (Tm ^ S) + (Tp ^ S), u, P) & valid;
-    } else {
-      // A row next to the cut: its temporal partner across the cut is in
-      // replica r+1 (t = 0) or r-1 (t = 1) for glued columns x < l.
+    philox10((uint32_t)((row - r * P.R) * G + w), g, j, ctr3 | ((uint32_t)r << 1), P.key0, P.key1, u);
+    uint32_t rmask = 0, rbit = 0;
+    if (t <= 1) {
+      // Row next to the cut: for glued columns x < l the temporal partner
+      // across the cut is in replica r+1 (t = 0) or r-1 (t = 1).
       const int rgl = (t == 0) ? ((r + 1 == P.n) ? 0 : r + 1) : ((r == 0) ? P.n - 1 : r - 1);
       const uint32_t Tg = Lo[(rgl * P.R + (1 - t) * P.ly + y) * G + w];
       const int v = P.l - p - 8 * w;  // bytes i with 8w + 2i + p < l are glued
       const int ng = (v <= 0) ? 0 : ((v + 1) >> 1);
       const uint32_t gm = (ng >= 4) ? 0xFFFFFFFFu : ((1u << (8 * ng)) - 1u);
       const uint32_t Tcut = (t == 0) ? Tp : Tm;  // own-replica partner across the cut
-      const uint32_t Tfix = (t == 0) ? Tm : Tp;  // temporal neighbour away from the cut
-      afix += Tfix ^ S;
       const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
-      flip = decide<DIM>(afix + (Teff ^ S), u, P) & valid;
+      a = a - (Tcut ^ S) + (Teff ^ S);
       if (p == ramp_p && w == ramp_w) {
-        // ramped site x = l: K = s (N a + (N-m) s_intra + m s_inter)
-        const uint32_t fa = (afix >> ramp_sh) & 0xFFu;
+        // ramped site x = l: K = s (N a_fix + (N-m) s_intra + m s_inter)
+        const uint32_t fa = ((a - (Teff ^ S)) >> ramp_sh) & 0xFFu;
         const uint32_t bb = ((Tcut ^ S) >> ramp_sh) & 1u;
         const uint32_t cc = ((Tg ^ S) >> ramp_sh) & 1u;
         const uint32_t U = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
         const uint32_t uu = (ramp_sh == 0) ? u[0] : (ramp_sh == 8) ? u[1] : (ramp_sh == 16) ? u[2] : u[3];
-        flip = (flip & ~(0xFFu << ramp_sh)) | ((uint32_t)(uu <= U) << ramp_sh);
+        rmask = 0xFFu << ramp_sh;
+        rbit = (uint32_t)(uu <= U) << ramp_sh;
         if (work) {
           // the ramped site of colour 0 sees phi_k: D_k term = 2 (b - c)
           const int d = 2 * ((int)bb - (int)cc);
@@ -191,7 +184,25 @@ __device__ __forceinline__ void half_sweep(const JP& P, uint32_t* __restrict__ L
         }
       }
     }
-    Lc[rowbase + w] = S ^ flip;
+    // acceptance: u <= thr[a] per site; the table offset is 4a = byte i of (a << 2)
+    const uint32_t a4 = a << 2;
+    uint32_t f = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
+                                                             ((a4 >> (8 * i)) & 0xFFu));
+      f |= (uint32_t)(u[i] <= th) << (8 * i);
+    }
+    f = ((f & ~rmask) | rbit) & valid;
+    Lc[rowbase + w] = S ^ f;
+    // next row of this lane
+    if (DIM == 3) {
+      y += ln.dy;
+      if (y >= P.ly) { y -= P.ly; ++t; }
+    }
+    t += ln.dt;
+    if (t >= P.lt) { t -= P.lt; ++r; }
+    r += ln.dr;
   }
 }
 
@@ -253,9 +264,9 @@ __device__ void store_spins(const JP& P, const uint32_t* L, uint32_t j, int lt_,
 }
 
 // All sweeps of one work unit: k trajectories of one job, one per LDS slot.
-template <int DIM>
-__device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, int j0, int cnt, int kslots,
-                                         uint32_t flags, int n_therm, int g0) {
+template <int DIM, bool FULL, bool UJ>
+__device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr, int j0,
+                                         int cnt, int kslots, uint32_t flags, int n_therm, int g0) {
   const int tid = threadIdx.x;
   const int T = blockDim.x / kslots;
   const int slot = tid / T;
@@ -264,31 +275,41 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
   uint32_t* L = lds + (size_t)slot * P.traj_words;
   const uint32_t j = (uint32_t)(j0 + slot);
   if (tid < ee::kMaxSlots) s_dI[tid] = 0;
+  if (tid < 8) s_thr[tid] = (tid == 0) ? P.thr0 : (tid == 1) ? P.thr1 : (tid == 2 && DIM == 3) ? P.thr2 : 0xFFFFFFFFu;
   if (active) {
     if (flags & ee::kFlagInit) init_spins(P, L, j, lt_, T);
     else load_spins(P, L, j, lt_, T);
   }
+  Lane ln;
+  ln.w = lt_ % P.G;
+  ln.wl = (ln.w == 0) ? P.G - 1 : ln.w - 1;
+  ln.wr = (ln.w == P.G - 1) ? 0 : ln.w + 1;
+  ln.row0 = lt_ / P.G;
+  ln.nrg = T / P.G;
+  ln.r0 = ln.row0 / P.R;
+  ln.t0 = (ln.row0 - ln.r0 * P.R) / P.ly;
+  ln.y0 = ln.row0 - ln.r0 * P.R - ln.t0 * P.ly;
+  ln.dr = ln.nrg / P.R;
+  ln.dt = (ln.nrg - ln.dr * P.R) / P.ly;
+  ln.dy = ln.nrg - ln.dr * P.R - ln.dt * P.ly;
+  const bool on = active && ln.row0 < ln.nrg;
   __syncthreads();
 
-  const int w = lt_ % P.G;
-  const int rg = lt_ / P.G;
-  const int nrg = T / P.G;
-  const bool on = active && rg < nrg;
   int dI = 0;
   uint32_t g = (uint32_t)g0;
   const int m0 = P.reverse ? P.N : 0;
   for (int s = 0; s < n_therm; ++s, ++g) {
-    if (on) half_sweep<DIM>(P, L, 0, w, rg, nrg, g, j, m0, false, dI);
+    if (on) half_sweep<DIM, FULL, UJ>(P, ln, L, s_thr, 0, g, j, m0, false, dI);
     __syncthreads();
-    if (on) half_sweep<DIM>(P, L, 1, w, rg, nrg, g, j, m0, false, dI);
+    if (on) half_sweep<DIM, FULL, UJ>(P, ln, L, s_thr, 1, g, j, m0, false, dI);
     __syncthreads();
   }
   if (flags & ee::kFlagProto) {
     for (int k = 0; k < P.N; ++k, ++g) {
       const int m = P.reverse ? P.N - 1 - k : k + 1;
-      if (on) half_sweep<DIM>(P, L, 0, w, rg, nrg, g, j, m, true, dI);
+      if (on) half_sweep<DIM, FULL, UJ>(P, ln, L, s_thr, 0, g, j, m, true, dI);
       __syncthreads();
-      if (on) half_sweep<DIM>(P, L, 1, w, rg, nrg, g, j, m, false, dI);
+      if (on) half_sweep<DIM, FULL, UJ>(P, ln, L, s_thr, 1, g, j, m, false, dI);
       __syncthreads();
     }
     if (dI != 0) atomicAdd(&s_dI[slot], dI);
@@ -299,16 +320,28 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
   __syncthreads();
 }
 
+template <int DIM>
+__device__ __forceinline__ void run_unit_dispatch(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr,
+                                                  int j0, int cnt, int kslots, uint32_t flags, int n_therm,
+                                                  int g0) {
+  const bool full = (P.H & 3) == 0;
+  const bool uj = ((blockDim.x / kslots) & 63) == 0;
+  if (full && uj) run_unit<DIM, true, true>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else if (full) run_unit<DIM, true, false>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else run_unit<DIM, false, false>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+}
+
 // Per-job mode (units == nullptr): workgroup b runs trajectories
 // [b*single_k, b*single_k + single_k) of single_job.  Batch mode: persistent
 // workgroups draw units from the queue until it is empty.  The dimension of
 // each unit's job selects the 2D or 3D sweep (uniform per workgroup).
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
 sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_units, int* queue,
              const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0) {
   extern __shared__ uint32_t lds[];
   __shared__ int s_unit;
   __shared__ int s_dI[ee::kMaxSlots];
+  __shared__ uint32_t s_thr[8];
   const int tid = threadIdx.x;
   for (int iter = 0;; ++iter) {
     const JobDev* J;
@@ -332,9 +365,9 @@ sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_un
     }
     const JP P = load_jp(J);
     if (uni(J->dim) == 3)
-      run_unit<3>(P, lds, s_dI, j0, cnt, kslots, flags, n_therm, g0);
+      run_unit_dispatch<3>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
     else
-      run_unit<2>(P, lds, s_dI, j0, cnt, kslots, flags, n_therm, g0);
+      run_unit_dispatch<2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
   }
 }
 

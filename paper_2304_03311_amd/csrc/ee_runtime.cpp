@@ -137,18 +137,22 @@ constexpr int kDefaultLdsBudget = 80 * 1024;  // two workgroups per CU
 
 // Trajectories per workgroup that maximise the trajectories finished per
 // unit of workgroup time, within the LDS budget.
-int choose_slots(const Layout& L, int n_rep, int block, int lds_budget, int n_traj) {
+// min_groups > 0 (per-job launches): keep at least that many workgroups so
+// that one job alone fills the GPU.
+int choose_slots(const Layout& L, int n_rep, int block, int lds_budget, int n_traj, int min_groups = 0) {
   const int traj_bytes = L.traj_words * 4;
   int kmax = std::min(ee::kMaxSlots, std::max(1, lds_budget / traj_bytes));
   kmax = std::min(kmax, std::max(1, block / L.G));
   kmax = std::min(kmax, std::max(1, n_traj));
+  if (min_groups > 0) kmax = std::min(kmax, std::max(1, n_traj / min_groups));
   const int nrows = n_rep * L.R;
+  // ties go to the larger k: more rows per lane between workgroup barriers
   int best_k = 1;
   double best = -1.0;
-  for (int k = 1; k <= kmax; ++k) {
+  for (int k = kmax; k >= 1; --k) {
     const int T = block / k;
     const int nrg = T / L.G;
-    if (nrg < 1) break;
+    if (nrg < 1) continue;
     const int iters = (nrows + nrg - 1) / nrg;
     const double rate = (double)k / iters;
     if (rate > best * 1.0001) {
@@ -240,7 +244,8 @@ bool same_cfg(const ee_launch_cfg& a, const ee_launch_cfg& b) {
 ee_status launch_sweep_for_job(ee_job* j, uint32_t flags, int n_therm) {
   const int block = j->cfg.block_threads > 0 ? j->cfg.block_threads : kDefaultBlock;
   const int budget = j->cfg.lds_bytes > 0 ? j->cfg.lds_bytes : kDefaultLdsBudget;
-  const int k = choose_slots(j->L, j->d.n_replicas, block, std::max(budget, j->L.traj_words * 4), j->d.n_traj);
+  const int k = choose_slots(j->L, j->d.n_replicas, block, std::max(budget, j->L.traj_words * 4), j->d.n_traj,
+                             2 * device_info().cus);
   const int grid = (j->d.n_traj + k - 1) / k;
   const int lds = k * j->L.traj_words * 4;
   const int rc = ee_k_launch_sweep(j->d.dim, j->dev_jobdev(), k, nullptr, 0, nullptr, nullptr, flags,
