@@ -64,6 +64,21 @@ def cpu_baseline(n_traj_sample: int) -> dict:
                       f"({att:.3g} attempts, {dt:.1f} s, single-threaded C oracle)"}
 
 
+def serving_run(n_jobs: int, rate: float = 200.0) -> dict:
+    """Poisson stream at `rate` jobs/s through the continuous-batching server."""
+    from paper_2304_03311_amd import serve, workloads
+    stream = workloads.serving_stream(n_jobs, rate, seed=1, **workloads.SERVE_MIX)
+    reqs = serve.requests_from_stream(stream)
+    offered = sum(s.n_traj * s.sites * (workloads.N_THERM + s.n_step) for _, s in stream) / stream[-1][0]
+    srv = serve.Server(hbm_budget_bytes=workloads.SERVE_HBM_BUDGET, slots=workloads.SERVE_SLOTS,
+                       n_therm=workloads.N_THERM)
+    srv.run(reqs, realtime=True)
+    out = srv.stats.summary()
+    out.update(rate_jobs_per_s=rate, offered_attempts_per_ns=offered / 1e9, mix=workloads.SERVE_MIX,
+               hbm_budget_bytes=workloads.SERVE_HBM_BUDGET, slots=workloads.SERVE_SLOTS)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +87,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32, help="oracle trajectories timed for cpu_baseline")
     ap.add_argument("--per-job", action="store_true", help="also time the per-job launch path")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency) measurement")
+    ap.add_argument("--serve-jobs", type=int, default=400)
+    ap.add_argument("--no-tune", action="store_true", help="library default launch shape instead of the tuner's")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device-to-device once (HBM counter calibration)")
     args = ap.parse_args()
@@ -83,19 +101,22 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_2304_03311_amd import analysis, ee, workloads
+    from paper_2304_03311_amd import analysis, autotune, ee, serve, workloads
 
     torch.cuda.set_device(0)
     specs = workloads.config2_jobs()
     stream = torch.cuda.current_stream()
-    jobs = [ee.Job(s, stream=stream) for s in specs]
     n_therm = workloads.N_THERM
+    launch = workloads.BENCH_LAUNCH
+    if not args.no_tune:
+        launch = autotune.cached(specs, n_therm) or autotune.tune(specs, n_therm, stream=stream)
+    jobs = [ee.Job(s, stream=stream) for s in specs]
     attempts_per_step = sum(s.n_traj * s.sites * (n_therm + s.n_step) for s in specs)
 
     def step():
         for j in jobs:
             j.reset()
-        ee.batch_run(jobs, n_therm, stream=stream, cfg=workloads.BENCH_LAUNCH)
+        ee.batch_run(jobs, n_therm, stream=stream, cfg=launch)
         res = [j.estimate() for j in jobs]
         return res, ee.ee_batch_kernel_ms()
 
@@ -148,6 +169,7 @@ def main() -> int:
                      "ops_per_attempt": ops_per_attempt(2),
                      "attempts_per_ns_in_kernel": attempts_per_step / (k_avg_s * 1e9)},
         "c2_fit_k": curve.get("fit_k"),
+        "launch": launch,
     }
     if args.per_job:
         t0 = time.perf_counter()
@@ -159,6 +181,8 @@ def main() -> int:
             j.estimate()
         torch.cuda.synchronize()
         out["per_job_path_attempts_per_ns"] = attempts_per_step / ((time.perf_counter() - t0) * 1e9)
+    if not args.no_serve:
+        out["serving"] = serving_run(args.serve_jobs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     for j in jobs:

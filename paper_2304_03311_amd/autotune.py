@@ -1,0 +1,81 @@
+"""Autotuner of the persistent sweep kernel's launch shape.
+
+The shape is the workgroup size (64..1024 threads) and the LDS budget per
+workgroup.  Together they fix how many trajectories share a workgroup (LDS
+slots), how many rows each lane walks between barriers, and how many
+workgroups stay resident per CU.  Every shape gives bit-identical results,
+because the random numbers are indexed by site, sweep and trajectory and
+never by thread.  So the tuner only measures time.
+
+Trials run the same job shapes with a shortened protocol.  The kernel time
+is measured with HIP events (ee_batch_kernel_ms).  The best shape is cached
+in a JSON file keyed by a signature of the job shapes.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import json
+import os
+
+from . import ee
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_launch.json")
+
+CANDIDATES = [
+    {"block_threads": b, "lds_bytes": lds, "grid_blocks": 0, "use_graph": 1}
+    for b in (256, 512, 1024)
+    for lds in (40 * 1024, 53 * 1024, 80 * 1024, 160 * 1024 - 256)
+]
+
+
+def signature(specs: list[ee.JobSpec], n_therm: int) -> str:
+    key = json.dumps([[s.dim, s.lt, s.lx, s.ly, s.n, s.n_step, s.n_traj, s.spin_format] for s in specs]
+                     + [n_therm])
+    return hashlib.sha256(key.encode()).hexdigest()[:16]
+
+
+def _load() -> dict:
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def cached(specs, n_therm):
+    return _load().get(signature(specs, n_therm))
+
+
+def tune(specs: list[ee.JobSpec], n_therm: int, trial_steps: int = 40, trial_therm: int = 8,
+         candidates=None, repeats: int = 2, stream=None, save: bool = True, verbose: bool = False) -> dict:
+    """Pick the fastest launch shape for this job set; returns the ee_launch_cfg dict."""
+    import torch
+    candidates = CANDIDATES if candidates is None else candidates
+    # same lattice shapes and trajectory counts, shorter protocol
+    trial_specs = [dataclasses.replace(s, n_step=min(s.n_step, trial_steps)) for s in specs]
+    jobs = [ee.Job(s, stream=stream) for s in trial_specs]
+    results = []
+    try:
+        for cfg in candidates:
+            times = []
+            for _ in range(repeats):
+                for j in jobs:
+                    j.reset()
+                ee.batch_run(jobs, trial_therm, stream=stream, cfg=cfg)
+                times.append(ee.ee_batch_kernel_ms())
+            t = min(times)
+            results.append((t, cfg))
+            if verbose:
+                print(f"autotune {cfg} -> {t:.3f} ms", flush=True)
+        torch.cuda.synchronize()
+    finally:
+        for j in jobs:
+            j.close()
+    results.sort(key=lambda x: x[0])
+    best = dict(results[0][1])
+    if save:
+        db = _load()
+        db[signature(specs, n_therm)] = best
+        with open(CACHE, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+    return best

@@ -30,8 +30,16 @@ BETA_C_2D = 0.5 * math.log(1.0 + math.sqrt(2.0))  # Sec. 4
 BETA_3D = 0.2216546                                 # Sec. 5 (beta_c = 0.221654626(5))
 N_THERM = 100
 
-# launch shape the benchmark times (None = library defaults)
+# launch shape the benchmark times when the tuner is off (None = library defaults)
 BENCH_LAUNCH = None
+
+# serving benchmark: size mix of the Poisson stream (tuned to about 60% of the
+# per-job path's measured capacity at 200 jobs/s), resident-job slots and the
+# HBM admission budget (288 GB of HBM3E minus a reserve for the rest of the
+# process)
+SERVE_MIX = {"max_l3": 40, "n_traj_choices": (64, 128, 256), "n_step_choices": (500, 1000)}
+SERVE_SLOTS = 16
+SERVE_HBM_BUDGET = 256 * 1024 ** 3
 
 
 def config1_job() -> JobSpec:
