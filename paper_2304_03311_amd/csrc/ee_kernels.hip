@@ -86,8 +86,9 @@ __device__ __forceinline__ JP load_jp(const JobDev* J) {
   return P;
 }
 
-// Per-lane iteration state of one work unit (the same for every sweep):
-// the lane owns word w of rows row0, row0 + nrg, ...; (r0, t0, y0) is the
+// Per-lane iteration state of one work unit (the same for every sweep): the
+// lane owns words w .. w+W-1 of rows row0, row0 + nrg, ...; wl / wr are the
+// words left and right of that group (periodic in x); (r0, t0, y0) is the
 // first row decoded and nrg = dr*R + dt*ly + dy the row stride.
 struct Lane {
   int w, wl, wr;
@@ -104,11 +105,13 @@ __device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) { re
 //        anti-aligned neighbours (2^32-1 for a >= DIM)
 // FULL: lx/2 is a multiple of 4 (no pad bytes, x-neighbours by byte
 // alignment of two words).  UJ: the trajectory index is uniform per wave.
-template <int DIM, bool FULL, bool UJ>
+// W: consecutive words per lane (2 needs FULL and an even word count).
+template <int DIM, bool FULL, bool UJ, int W>
 __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t* __restrict__ L,
                                            const uint32_t* __restrict__ thr, const int c,
                                            const uint32_t g, uint32_t j, const int m,
                                            const bool work, int& dI) {
+  static_assert(W == 1 || (W == 2 && FULL), "two words per lane need whole rows");
   if (UJ) j = __builtin_amdgcn_readfirstlane(j);
   const int G = P.G;
   const int cw = P.n * P.R * G;  // words per colour plane
@@ -131,70 +134,96 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
   const int step = ln.nrg * G;
   for (int row = ln.row0; row < nrows; row += ln.nrg, rowbase += step) {
     const int p = (c + t + y) & 1;  // x parity of this row's sites
-    uint32_t A, B;
+    uint32_t A[W], B[W], S[W], a[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) A[q] = Lo[rowbase + w + q];
     if (FULL) {
-      // the sites' x-1 (p = 0) or x+1 (p = 1) neighbours straddle words (w-1, w) or (w, w+1)
-      const uint32_t lo = Lo[rowbase + (p ? w : ln.wl)];
-      const uint32_t hi = Lo[rowbase + (p ? ln.wr : w)];
-      B = __builtin_amdgcn_alignbyte(hi, lo, p ? 1u : 3u);
-      A = p ? lo : hi;
+      // the sites' x-1 (p = 0) or x+1 (p = 1) neighbours straddle two words
+      const uint32_t E = Lo[rowbase + (p ? ln.wr : ln.wl)];
+      const uint32_t sh = p ? 1u : 3u;
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        const uint32_t nxt = (q + 1 < W) ? A[q + 1] : E;
+        const uint32_t prv = (q > 0) ? A[q - 1] : E;
+        B[q] = __builtin_amdgcn_alignbyte(p ? nxt : A[q], p ? A[q] : prv, sh);
+      }
     } else {
-      A = Lo[rowbase + w];
       const uint32_t nb = Lo[rowbase + (p ? ln.wr : ln.wl)];
-      const uint32_t Br = (A >> 8) | ((nb & 0xFFu) << rshift);
-      const uint32_t Bl = (A << 8) | ((w == 0) ? ((nb >> tailsh) & 0xFFu) : (nb >> 24));
-      B = p ? Br : Bl;
+      const uint32_t Br = (A[0] >> 8) | ((nb & 0xFFu) << rshift);
+      const uint32_t Bl = (A[0] << 8) | ((w == 0) ? ((nb >> tailsh) & 0xFFu) : (nb >> 24));
+      B[0] = p ? Br : Bl;
     }
-    const uint32_t S = Lc[rowbase + w];
-    const uint32_t Tm = Lo[rowbase + ((t == 0) ? twrap : -LyG) + w];
-    const uint32_t Tp = Lo[rowbase + ((t == P.lt - 1) ? -twrap : LyG) + w];
-    uint32_t a = xad(A, S, xad(B, S, xad(Tm, S, Tp ^ S)));
+    const int om = rowbase + ((t == 0) ? twrap : -LyG) + w;
+    const int op = rowbase + ((t == P.lt - 1) ? -twrap : LyG) + w;
+    uint32_t Tm[W], Tp[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      S[q] = Lc[rowbase + w + q];
+      Tm[q] = Lo[om + q];
+      Tp[q] = Lo[op + q];
+      a[q] = xad(A[q], S[q], xad(B[q], S[q], xad(Tm[q], S[q], Tp[q] ^ S[q])));
+    }
     if (DIM == 3) {
-      const uint32_t Ym = Lo[rowbase + ((y == 0) ? ywrap : -G) + w];
-      const uint32_t Yp = Lo[rowbase + ((y == P.ly - 1) ? -ywrap : G) + w];
-      a = xad(Ym, S, xad(Yp, S, a));
+      const int oym = rowbase + ((y == 0) ? ywrap : -G) + w;
+      const int oyp = rowbase + ((y == P.ly - 1) ? -ywrap : G) + w;
+#pragma unroll
+      for (int q = 0; q < W; ++q) a[q] = xad(Lo[oym + q], S[q], xad(Lo[oyp + q], S[q], a[q]));
     }
-    uint32_t u[4];
-    philox10((uint32_t)((row - r * P.R) * G + w), g, j, ctr3 | ((uint32_t)r << 1), P.key0, P.key1, u);
-    uint32_t rmask = 0, rbit = 0;
+    uint32_t u[W][4];
+    const uint32_t c0 = (uint32_t)((row - r * P.R) * G + w);
+    const uint32_t c3 = ctr3 | ((uint32_t)r << 1);
+#pragma unroll
+    for (int q = 0; q < W; ++q) philox10(c0 + q, g, j, c3, P.key0, P.key1, u[q]);
+    uint32_t rmask[W], rbit[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) rmask[q] = rbit[q] = 0;
     if (t <= 1) {
       // Row next to the cut: for glued columns x < l the temporal partner
       // across the cut is in replica r+1 (t = 0) or r-1 (t = 1).
       const int rgl = (t == 0) ? ((r + 1 == P.n) ? 0 : r + 1) : ((r == 0) ? P.n - 1 : r - 1);
-      const uint32_t Tg = Lo[(rgl * P.R + (1 - t) * P.ly + y) * G + w];
-      const int v = P.l - p - 8 * w;  // bytes i with 8w + 2i + p < l are glued
-      const int ng = (v <= 0) ? 0 : ((v + 1) >> 1);
-      const uint32_t gm = (ng >= 4) ? 0xFFFFFFFFu : ((1u << (8 * ng)) - 1u);
-      const uint32_t Tcut = (t == 0) ? Tp : Tm;  // own-replica partner across the cut
-      const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
-      a = a - (Tcut ^ S) + (Teff ^ S);
-      if (p == ramp_p && w == ramp_w) {
-        // ramped site x = l: K = s (N a_fix + (N-m) s_intra + m s_inter)
-        const uint32_t fa = ((a - (Teff ^ S)) >> ramp_sh) & 0xFFu;
-        const uint32_t bb = ((Tcut ^ S) >> ramp_sh) & 1u;
-        const uint32_t cc = ((Tg ^ S) >> ramp_sh) & 1u;
-        const uint32_t U = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
-        const uint32_t uu = (ramp_sh == 0) ? u[0] : (ramp_sh == 8) ? u[1] : (ramp_sh == 16) ? u[2] : u[3];
-        rmask = 0xFFu << ramp_sh;
-        rbit = (uint32_t)(uu <= U) << ramp_sh;
-        if (work) {
-          // the ramped site of colour 0 sees phi_k: D_k term = 2 (b - c)
-          const int d = 2 * ((int)bb - (int)cc);
-          dI += P.reverse ? -d : d;
+      const int og = (rgl * P.R + (1 - t) * P.ly + y) * G + w;
+      const uint32_t t0mask = (t == 0) ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        const uint32_t Tg = Lo[og + q];
+        const int v = P.l - p - 8 * (w + q);  // bytes i with 8(w+q) + 2i + p < l are glued
+        const int ng = (v <= 0) ? 0 : ((v + 1) >> 1);
+        const uint32_t gm = (ng >= 4) ? 0xFFFFFFFFu : ((1u << (8 * ng)) - 1u);
+        // own-replica partner across the cut: Tp on t = 0, Tm on t = 1
+        const uint32_t Tcut = (Tp[q] & t0mask) | (Tm[q] & ~t0mask);
+        const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
+        a[q] = a[q] - (Tcut ^ S[q]) + (Teff ^ S[q]);
+        if (p == ramp_p && w + q == ramp_w) {
+          // ramped site x = l: K = s (N a_fix + (N-m) s_intra + m s_inter)
+          const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
+          const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
+          const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
+          const uint32_t U = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
+          const uint32_t uu = (ramp_sh == 0) ? u[q][0] : (ramp_sh == 8) ? u[q][1] : (ramp_sh == 16) ? u[q][2] : u[q][3];
+          rmask[q] = 0xFFu << ramp_sh;
+          rbit[q] = (uint32_t)(uu <= U) << ramp_sh;
+          if (work) {
+            // the ramped site of colour 0 sees phi_k: D_k term = 2 (b - c)
+            const int d = 2 * ((int)bb - (int)cc);
+            dI += P.reverse ? -d : d;
+          }
         }
       }
     }
-    // acceptance: u <= thr[a] per site; the table offset is 4a = byte i of (a << 2)
-    const uint32_t a4 = a << 2;
-    uint32_t f = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
-                                                             ((a4 >> (8 * i)) & 0xFFu));
-      f |= (uint32_t)(u[i] <= th) << (8 * i);
+    for (int q = 0; q < W; ++q) {
+      // acceptance: u <= thr[a] per site; the table offset is 4a = byte i of (a << 2)
+      const uint32_t a4 = a[q] << 2;
+      uint32_t f = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
+                                                               ((a4 >> (8 * i)) & 0xFFu));
+        f |= (uint32_t)(u[q][i] <= th) << (8 * i);
+      }
+      f = ((f & ~rmask[q]) | rbit[q]) & valid;
+      Lc[rowbase + w + q] = S[q] ^ f;
     }
-    f = ((f & ~rmask) | rbit) & valid;
-    Lc[rowbase + w] = S ^ f;
     // next row of this lane
     if (DIM == 3) {
       y += ln.dy;
@@ -264,7 +293,7 @@ __device__ void store_spins(const JP& P, const uint32_t* L, uint32_t j, int lt_,
 }
 
 // All sweeps of one work unit: k trajectories of one job, one per LDS slot.
-template <int DIM, bool FULL, bool UJ>
+template <int DIM, bool FULL, bool UJ, int W>
 __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr, int j0,
                                          int cnt, int kslots, uint32_t flags, int n_therm, int g0) {
   const int tid = threadIdx.x;
@@ -280,12 +309,13 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
     if (flags & ee::kFlagInit) init_spins(P, L, j, lt_, T);
     else load_spins(P, L, j, lt_, T);
   }
+  const int GW = P.G / W;  // word groups per row
   Lane ln;
-  ln.w = lt_ % P.G;
+  ln.w = (lt_ % GW) * W;
   ln.wl = (ln.w == 0) ? P.G - 1 : ln.w - 1;
-  ln.wr = (ln.w == P.G - 1) ? 0 : ln.w + 1;
-  ln.row0 = lt_ / P.G;
-  ln.nrg = T / P.G;
+  ln.wr = (ln.w + W == P.G) ? 0 : ln.w + W;
+  ln.row0 = lt_ / GW;
+  ln.nrg = T / GW;
   ln.r0 = ln.row0 / P.R;
   ln.t0 = (ln.row0 - ln.r0 * P.R) / P.ly;
   ln.y0 = ln.row0 - ln.r0 * P.R - ln.t0 * P.ly;
@@ -299,17 +329,17 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
   uint32_t g = (uint32_t)g0;
   const int m0 = P.reverse ? P.N : 0;
   for (int s = 0; s < n_therm; ++s, ++g) {
-    if (on) half_sweep<DIM, FULL, UJ>(P, ln, L, s_thr, 0, g, j, m0, false, dI);
+    if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 0, g, j, m0, false, dI);
     __syncthreads();
-    if (on) half_sweep<DIM, FULL, UJ>(P, ln, L, s_thr, 1, g, j, m0, false, dI);
+    if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 1, g, j, m0, false, dI);
     __syncthreads();
   }
   if (flags & ee::kFlagProto) {
     for (int k = 0; k < P.N; ++k, ++g) {
       const int m = P.reverse ? P.N - 1 - k : k + 1;
-      if (on) half_sweep<DIM, FULL, UJ>(P, ln, L, s_thr, 0, g, j, m, true, dI);
+      if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 0, g, j, m, true, dI);
       __syncthreads();
-      if (on) half_sweep<DIM, FULL, UJ>(P, ln, L, s_thr, 1, g, j, m, false, dI);
+      if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 1, g, j, m, false, dI);
       __syncthreads();
     }
     if (dI != 0) atomicAdd(&s_dI[slot], dI);
@@ -320,15 +350,25 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
   __syncthreads();
 }
 
+// Words per lane for a job and slot size: two when rows are whole words in
+// pairs and every row still gets a lane group.
+__device__ __forceinline__ int words_per_lane(const JP& P, int T) {
+  return ((P.H & 7) == 0 && T / (P.G / 2) >= 1) ? 2 : 1;
+}
+
 template <int DIM>
 __device__ __forceinline__ void run_unit_dispatch(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr,
                                                   int j0, int cnt, int kslots, uint32_t flags, int n_therm,
                                                   int g0) {
+  const int T = blockDim.x / kslots;
   const bool full = (P.H & 3) == 0;
-  const bool uj = ((blockDim.x / kslots) & 63) == 0;
-  if (full && uj) run_unit<DIM, true, true>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else if (full) run_unit<DIM, true, false>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else run_unit<DIM, false, false>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  const bool uj = (T & 63) == 0;
+  const bool two = words_per_lane(P, T) == 2;
+  if (two && uj) run_unit<DIM, true, true, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else if (two) run_unit<DIM, true, false, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else if (full && uj) run_unit<DIM, true, true, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else if (full) run_unit<DIM, true, false, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else run_unit<DIM, false, false, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
 }
 
 // Per-job mode (units == nullptr): workgroup b runs trajectories
