@@ -116,7 +116,8 @@ typedef struct ee_job ee_job; /* opaque host-side handle */
 
 /* Device bytes a job needs (spins of every trajectory, works, threshold
  * tables, result).  No device work.  EE_EINVAL for a bad description,
- * EE_EUNSUPPORTED if one trajectory does not fit the on-chip (LDS) tile. */
+ * EE_EUNSUPPORTED for a bit-packed job whose trajectory does not fit the
+ * on-chip (LDS) tile (such lattices are streamed from HBM in INT8). */
 ee_status ee_job_footprint(const ee_job_desc* desc, size_t* bytes);
 
 /* Validate desc, build the geometry and the uint32 threshold tables on the
@@ -168,6 +169,7 @@ ee_status ee_job_reset(ee_job* job);
  * HIP graph and replayed when the same jobs are run again.  All jobs end in
  * DONE; their results are then read with ee_estimate.  Results are
  * bit-identical to the per-job path (ee_thermalize + ee_run_protocol).
+ * Jobs on the HBM-streaming path are rejected with EE_EUNSUPPORTED.
  * hip_stream: stream of the batch (the jobs' own streams are not used). */
 ee_status ee_batch_run(ee_job* const* jobs, int32_t count, int32_t n_therm, void* hip_stream);
 
@@ -177,7 +179,15 @@ typedef struct {
   int32_t lds_bytes;       /* LDS budget per workgroup (bytes); 0 = default               */
   int32_t grid_blocks;     /* persistent workgroups; 0 = one wave of the whole GPU          */
   int32_t use_graph;       /* 1 = record/replay a HIP graph (default), 0 = direct launches  */
+  uint32_t flags;          /* EE_LAUNCH_* bits                                            */
 } ee_launch_cfg;
+
+/* ee_launch_cfg.flags: run a job on the HBM-streaming path even if its
+ * trajectories fit on chip (per-job path only; needs EE_SPINS_INT8).  Jobs
+ * whose trajectory exceeds one workgroup's LDS always use that path: the
+ * spins stay in HBM and every half-sweep is one launch over all
+ * trajectories, with bit-identical results. */
+#define EE_LAUNCH_STREAMING 1u
 
 /* ee_batch_run with an explicit launch shape (NULL = defaults). */
 ee_status ee_batch_run_cfg(ee_job* const* jobs, int32_t count, int32_t n_therm,

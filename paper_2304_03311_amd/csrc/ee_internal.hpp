@@ -82,4 +82,8 @@ int ee_k_sweep_kernel_ptr(int dim, const void** fn);
 int ee_k_queue_reset_ptr(const void** fn);
 int ee_k_estimate_ptr(const void** fn);
 int ee_k_max_lds_bytes();
+int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int m, int work,
+                             void* stream);
+int ee_k_launch_stream_init(const ee::JobDev* job, int n_traj, int lanes, void* stream);
+int ee_k_launch_zero_work(const ee::JobDev* job, int n_traj, void* stream);
 }

@@ -411,6 +411,74 @@ sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_un
   }
 }
 
+// ---------------------------------------------------------------------------
+// Streaming path: lattices larger than one workgroup's LDS.  The spins stay
+// in HBM (INT8 colour planes); one launch updates one colour of every
+// trajectory of a job.  Block (x, y) covers lanes of trajectory y; a
+// trajectory has `lanes` lanes, each walking its rows as in the on-chip
+// path.  The neighbour rows are read through the vector caches, and the
+// integer work goes to HBM with 64-bit atomics.
+// ---------------------------------------------------------------------------
+template <int DIM, bool FULL, int W>
+__device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int lanes, int c, uint32_t g, int m,
+                                            bool work) {
+  const int lt_ = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t j = blockIdx.y;
+  uint32_t* L = P.spins + (size_t)j * P.traj_words;
+  const int GW = P.G / W;
+  Lane ln;
+  ln.w = (lt_ % GW) * W;
+  ln.wl = (ln.w == 0) ? P.G - 1 : ln.w - 1;
+  ln.wr = (ln.w + W == P.G) ? 0 : ln.w + W;
+  ln.row0 = lt_ / GW;
+  ln.nrg = lanes / GW;
+  ln.r0 = ln.row0 / P.R;
+  ln.t0 = (ln.row0 - ln.r0 * P.R) / P.ly;
+  ln.y0 = ln.row0 - ln.r0 * P.R - ln.t0 * P.ly;
+  ln.dr = ln.nrg / P.R;
+  ln.dt = (ln.nrg - ln.dr * P.R) / P.ly;
+  ln.dy = ln.nrg - ln.dr * P.R - ln.dt * P.ly;
+  int dI = 0;
+  if (lt_ < lanes && ln.row0 < ln.nrg) half_sweep<DIM, FULL, true, W>(P, ln, L, s_thr, c, g, j, m, work, dI);
+  if (dI != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.work[j]), (unsigned long long)(long long)dI);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int m, int work) {
+  __shared__ uint32_t s_thr[8];
+  const JP P = load_jp(J);
+  const int dim = uni(J->dim);
+  if (threadIdx.x < 8)
+    s_thr[threadIdx.x] = (threadIdx.x == 0) ? P.thr0 : (threadIdx.x == 1) ? P.thr1
+                       : (threadIdx.x == 2 && dim == 3) ? P.thr2 : 0xFFFFFFFFu;
+  __syncthreads();
+  const bool two = words_per_lane(P, lanes) == 2;
+  const bool full = (P.H & 3) == 0;
+  if (dim == 3) {
+    if (two) stream_half<3, true, 2>(P, s_thr, lanes, c, g, m, work != 0);
+    else if (full) stream_half<3, true, 1>(P, s_thr, lanes, c, g, m, work != 0);
+    else stream_half<3, false, 1>(P, s_thr, lanes, c, g, m, work != 0);
+  } else {
+    if (two) stream_half<2, true, 2>(P, s_thr, lanes, c, g, m, work != 0);
+    else if (full) stream_half<2, true, 1>(P, s_thr, lanes, c, g, m, work != 0);
+    else stream_half<2, false, 1>(P, s_thr, lanes, c, g, m, work != 0);
+  }
+}
+
+// Initial spins of every trajectory, written straight to HBM.
+__global__ void __launch_bounds__(256) stream_init_kernel(const JobDev* J, int lanes) {
+  const JP P = load_jp(J);
+  const uint32_t j = blockIdx.y;
+  const int lt_ = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lt_ < lanes) init_spins(P, P.spins + (size_t)j * P.traj_words, j, lt_, lanes);
+}
+
+__global__ void zero_work_kernel(const JobDev* J) {
+  const int n = J->n_traj;
+  int64_t* w = J->work;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) w[i] = 0;
+}
+
 __global__ void queue_reset_kernel(int* queue) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
 }
@@ -554,6 +622,26 @@ int ee_k_launch_sweep(int dim, const ee::JobDev* single_job, int single_k, const
   (void)dim;
   hipLaunchKernelGGL(sweep_kernel, dim3(grid), dim3(block), lds_bytes, (hipStream_t)stream, single_job,
                      single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
+  return (int)hipGetLastError();
+}
+
+int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int m, int work,
+                             void* stream) {
+  const int bx = (lanes + 255) / 256;
+  hipLaunchKernelGGL(stream_sweep_kernel, dim3(bx, n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c, g,
+                     m, work);
+  return (int)hipGetLastError();
+}
+
+int ee_k_launch_stream_init(const ee::JobDev* job, int n_traj, int lanes, void* stream) {
+  const int bx = (lanes + 255) / 256;
+  hipLaunchKernelGGL(stream_init_kernel, dim3(bx, n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes);
+  return (int)hipGetLastError();
+}
+
+int ee_k_launch_zero_work(const ee::JobDev* job, int n_traj, void* stream) {
+  const int bx = (n_traj + 255) / 256;
+  hipLaunchKernelGGL(zero_work_kernel, dim3(bx), dim3(256), 0, (hipStream_t)stream, job);
   return (int)hipGetLastError();
 }
 

@@ -181,6 +181,7 @@ struct ee_job {
   bool est_enqueued;
   hipStream_t est_stream;
   ee_launch_cfg cfg;
+  bool streaming;  // spins stay in HBM (one launch per half-sweep)
   ee::JobDev* dev_jobdev() const { return reinterpret_cast<ee::JobDev*>(arena + L.off_jobdev); }
   const ee::JobDev* const* dev_selfptr() const {
     return reinterpret_cast<const ee::JobDev* const*>(arena + L.off_selfptr);
@@ -238,10 +239,44 @@ void drop_plans_with(ee_job* j) {
 
 bool same_cfg(const ee_launch_cfg& a, const ee_launch_cfg& b) {
   return a.block_threads == b.block_threads && a.lds_bytes == b.lds_bytes &&
-         a.grid_blocks == b.grid_blocks && a.use_graph == b.use_graph;
+         a.grid_blocks == b.grid_blocks && a.use_graph == b.use_graph && a.flags == b.flags;
+}
+
+// Lanes per trajectory of the streaming path: every lane walks about 8 rows.
+int stream_lanes(const ee_job* j) {
+  const int nrows = j->d.n_replicas * j->L.R;
+  const int W = ((j->L.H & 7) == 0) ? 2 : 1;
+  const int GW = j->L.G / W;
+  const int nrg = std::max(1, (nrows + 7) / 8);
+  return nrg * GW;
+}
+
+ee_status stream_sweeps(ee_job* j, int n_sweeps, bool protocol) {
+  const int lanes = stream_lanes(j);
+  const int nt = j->d.n_traj;
+  int rc = 0;
+  if (protocol) rc = ee_k_launch_zero_work(j->dev_jobdev(), nt, j->stream);
+  uint32_t g = (uint32_t)j->g;
+  const int N = j->d.n_step;
+  const bool rev = (j->d.flags & EE_FLAG_REVERSE) != 0;
+  for (int s = 0; s < n_sweeps && rc == 0; ++s, ++g) {
+    const int m = protocol ? (rev ? N - 1 - s : s + 1) : (rev ? N : 0);
+    rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 0, g, m, protocol ? 1 : 0, j->stream);
+    if (rc == 0) rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 1, g, m, 0, j->stream);
+  }
+  if (rc) return fail(EE_EHIP, "streaming sweep launch failed: %s", hipGetErrorString((hipError_t)rc));
+  return EE_OK;
 }
 
 ee_status launch_sweep_for_job(ee_job* j, uint32_t flags, int n_therm) {
+  if (j->streaming) {
+    if (flags & ee::kFlagInit) {
+      const int rc = ee_k_launch_stream_init(j->dev_jobdev(), j->d.n_traj, stream_lanes(j), j->stream);
+      if (rc) return fail(EE_EHIP, "streaming init launch failed: %s", hipGetErrorString((hipError_t)rc));
+    }
+    if (flags & ee::kFlagProto) return stream_sweeps(j, j->d.n_step, true);
+    return stream_sweeps(j, n_therm, false);
+  }
   const int block = j->cfg.block_threads > 0 ? j->cfg.block_threads : kDefaultBlock;
   const int budget = j->cfg.lds_bytes > 0 ? j->cfg.lds_bytes : kDefaultLdsBudget;
   const int k = choose_slots(j->L, j->d.n_replicas, block, std::max(budget, j->L.traj_words * 4), j->d.n_traj,
@@ -262,6 +297,7 @@ ee_status check_cfg(const ee_launch_cfg* cfg) {
   if (cfg->lds_bytes < 0 || cfg->lds_bytes > ee_k_max_lds_bytes())
     return fail(EE_EINVAL, "lds_bytes must be in [0, %d]", ee_k_max_lds_bytes());
   if (cfg->grid_blocks < 0) return fail(EE_EINVAL, "grid_blocks must be >= 0");
+  if (cfg->flags & ~EE_LAUNCH_STREAMING) return fail(EE_EINVAL, "unknown launch flags 0x%x", cfg->flags);
   return EE_OK;
 }
 
@@ -403,9 +439,10 @@ ee_status ee_job_footprint(const ee_job_desc* desc, size_t* bytes) {
   ee_status s = validate(desc);
   if (s) return s;
   Layout L = layout_of(desc);
-  if (L.traj_words * 4 > ee_k_max_lds_bytes())
-    return fail(EE_EUNSUPPORTED, "one trajectory needs %d bytes of LDS (max %d)", L.traj_words * 4,
-                ee_k_max_lds_bytes());
+  if (L.traj_words * 4 > ee_k_max_lds_bytes() && desc->spin_format != EE_SPINS_INT8)
+    return fail(EE_EUNSUPPORTED,
+                "a trajectory of %d bytes exceeds the on-chip tile (%d bytes); such lattices are streamed "
+                "from HBM and need EE_SPINS_INT8 storage", L.traj_words * 4, ee_k_max_lds_bytes());
   *bytes = L.total;
   return EE_OK;
 }
@@ -432,7 +469,8 @@ ee_status ee_job_create(const ee_job_desc* desc, void* dev_arena, size_t arena_b
   j->n_therm_total = 0;
   j->est_enqueued = false;
   j->est_stream = j->stream;
-  j->cfg = ee_launch_cfg{0, 0, 0, 1};
+  j->cfg = ee_launch_cfg{0, 0, 0, 1, 0};
+  j->streaming = j->L.traj_words * 4 > ee_k_max_lds_bytes();
   const int dim = desc->dim, N = desc->n_step;
   // thresholds
   ee::JobDev& D = j->host_jobdev;
@@ -483,7 +521,13 @@ ee_status ee_job_set_launch(ee_job* job, const ee_launch_cfg* cfg) {
   if (!job) return fail(EE_EINVAL, "job is NULL");
   ee_status s = check_cfg(cfg);
   if (s) return s;
-  job->cfg = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1};
+  const bool force_stream = cfg && (cfg->flags & EE_LAUNCH_STREAMING);
+  if (force_stream && job->d.spin_format != EE_SPINS_INT8)
+    return fail(EE_EUNSUPPORTED, "the streaming path needs EE_SPINS_INT8 storage");
+  if (force_stream && job->spins_exist && !job->streaming)
+    return fail(EE_ESTATE, "switch to the streaming path before the first ee_thermalize");
+  job->cfg = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1, 0};
+  job->streaming = force_stream || job->L.traj_words * 4 > ee_k_max_lds_bytes();
   return EE_OK;
 }
 
@@ -606,11 +650,14 @@ ee_status ee_batch_run_cfg(ee_job* const* jobs, int32_t count, int32_t n_therm, 
   if (n_therm < 0) return fail(EE_EINVAL, "n_therm must be >= 0");
   ee_status s = check_cfg(cfg);
   if (s) return s;
-  ee_launch_cfg c = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1};
+  ee_launch_cfg c = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1, 0};
   for (int i = 0; i < count; ++i) {
     if (!jobs[i]) return fail(EE_EINVAL, "jobs[%d] is NULL", i);
     if (jobs[i]->state != CREATED || jobs[i]->spins_exist)
       return fail(EE_ESTATE, "jobs[%d] is not freshly created (use ee_job_reset)", i);
+    if (jobs[i]->streaming)
+      return fail(EE_EUNSUPPORTED, "jobs[%d] is too large for the on-chip batch kernel; run it with "
+                  "ee_thermalize / ee_run_protocol", i);
     for (int k = 0; k < i; ++k)
       if (jobs[k] == jobs[i]) return fail(EE_EINVAL, "jobs[%d] appears twice", i);
     if ((int64_t)n_therm + jobs[i]->d.n_step > 0x7FFFFFFF) return fail(EE_EINVAL, "sweep counter overflow");

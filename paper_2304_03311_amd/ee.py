@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libee.so")
 EE_OK, EE_EINVAL, EE_ENOMEM, EE_EHIP, EE_ESTATE, EE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 EE_SPINS_INT8, EE_SPINS_BITPACKED = 0, 1
 EE_FLAG_REVERSE = 1
+EE_LAUNCH_STREAMING = 1
 
 
 class ee_job_desc(ctypes.Structure):
@@ -39,7 +40,7 @@ class ee_result(ctypes.Structure):
 
 class ee_launch_cfg(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("grid_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class EEError(RuntimeError):
@@ -150,7 +151,7 @@ def _cfg(cfg) -> ee_launch_cfg | None:
     if isinstance(cfg, ee_launch_cfg):
         return cfg
     return ee_launch_cfg(int(cfg.get("block_threads", 0)), int(cfg.get("lds_bytes", 0)),
-                         int(cfg.get("grid_blocks", 0)), int(cfg.get("use_graph", 1)))
+                         int(cfg.get("grid_blocks", 0)), int(cfg.get("use_graph", 1)), int(cfg.get("flags", 0)))
 
 
 def ee_batch_run(jobs: list[int], n_therm: int, stream: int, cfg=None) -> None:

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(ee.ee_job_desc) == 56
     assert ctypes.sizeof(ee.ee_result) == 80
-    assert ctypes.sizeof(ee.ee_launch_cfg) == 16
+    assert ctypes.sizeof(ee.ee_launch_cfg) == 20
 
 
 def _spec(**kw):
@@ -78,9 +78,10 @@ def test_unknown_flags_rejected():
         ee.ee_job_footprint(d)
 
 
-def test_too_large_for_lds_is_unsupported():
+def test_too_large_for_lds_streams_in_int8_only():
+    assert ee.ee_job_footprint(_spec(dim=3, lt=96, lx=96, ly=96).desc()) > 2 * 96 ** 3 * 4
     with pytest.raises(ee.EEError) as ei:
-        ee.ee_job_footprint(_spec(dim=3, lt=96, lx=96, ly=96).desc())
+        ee.ee_job_footprint(_spec(dim=3, lt=96, lx=96, ly=96, spin_format=1).desc())
     assert ei.value.status == ee.EE_EUNSUPPORTED
 
 

@@ -237,3 +237,45 @@ def test_full_size_3d_32cube_sampled():
     assert np.all(np.abs(I) <= 2 * s.n * s.ly * s.n_step)
     check_estimate(job.estimate(), I, s)
     job.close()
+
+
+STREAM_CASES = [c for c in CASES if c[1].get("spin_format", 0) == 0 and c[1]["n_traj"] <= 16]
+
+
+@pytest.mark.parametrize("name,kw,n_therm", STREAM_CASES, ids=[c[0] for c in STREAM_CASES])
+def test_streaming_path_matches_oracle(name, kw, n_therm):
+    """The HBM-streaming path (one launch per half-sweep), forced on lattices
+    that would fit on chip, is bit-identical to the oracle."""
+    s = ee.JobSpec(**kw)
+    say(f"[gpu] streaming {name}")
+    job = ee.Job(s)
+    job.set_launch({"flags": ee.EE_LAUNCH_STREAMING})
+    job.thermalize(n_therm // 2)
+    job.thermalize(n_therm - n_therm // 2)
+    job.run_protocol()
+    I_or, sp_or = eo.run(oracle_job(s), n_therm, want_spins=True)
+    assert np.array_equal(job.work(), I_or)
+    assert np.array_equal(job.spins(), sp_or)
+    check_estimate(job.estimate(), I_or, s)
+    job.close()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dim=3, lt=48, lx=48, ly=48, n=2, beta=BC3, l=20, n_step=10, n_traj=4, seed=31),
+    dict(dim=2, lt=1024, lx=128, ly=1, n=2, beta=BC2, l=64, n_step=6, n_traj=2, seed=32, reverse=True),
+], ids=["3d_48cube", "2d_1024x128"])
+def test_lattices_beyond_lds_stream_from_hbm(kw):
+    s = ee.JobSpec(**kw)
+    say(f"[gpu] large lattice {kw}")
+    job = ee.Job(s)
+    job.thermalize(4)
+    job.run_protocol()
+    I_or, sp_or = eo.run(oracle_job(s), 4, want_spins=True)
+    assert np.array_equal(job.work(), I_or)
+    assert np.array_equal(job.spins(), sp_or)
+    check_estimate(job.estimate(), I_or, s)
+    with pytest.raises(ee.EEError) as e:
+        j2 = ee.Job(s)
+        ee.batch_run([j2], 1)
+    assert e.value.status == ee.EE_EUNSUPPORTED
+    job.close()
