@@ -79,6 +79,29 @@ def serving_run(n_jobs: int, rate: float = 200.0) -> dict:
     return out
 
 
+def streaming_run() -> dict:
+    """Throughput of the HBM-streaming path on the largest serving shape
+    (3D 96^3, n = 2, 32 trajectories, N = 100 after 10 thermalisation sweeps)."""
+    import torch
+    from paper_2304_03311_amd import ee, workloads
+    spec = ee.JobSpec(dim=3, lt=96, lx=96, ly=96, n=2, beta=workloads.BETA_3D, l=40, n_step=100, n_traj=32,
+                      seed=5)
+    job = ee.Job(spec)
+    job.thermalize(2)  # warm-up launches
+    torch.cuda.synchronize()
+    job.reset()
+    t0 = time.perf_counter()
+    job.thermalize(10)
+    job.run_protocol()
+    r = job.estimate()
+    dt = time.perf_counter() - t0
+    job.close()
+    return {"workload": "3D 96^3, n=2, n_t=32, N=100, N_therm=10, int8 in HBM", "attempts_per_ns": r.attempts / (dt * 1e9),
+            "ms": dt * 1e3, "launches": 2 * 110 + 3,
+            "algorithmic_bytes_per_attempt": 1.5,
+            "hbm_GBps_algorithmic": 1.5 * r.attempts / dt / 1e9}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +206,7 @@ def main() -> int:
         out["per_job_path_attempts_per_ns"] = attempts_per_step / ((time.perf_counter() - t0) * 1e9)
     if not args.no_serve:
         out["serving"] = serving_run(args.serve_jobs)
+        out["streaming_path"] = streaming_run()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     for j in jobs:

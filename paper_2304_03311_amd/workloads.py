@@ -37,7 +37,8 @@ BENCH_LAUNCH = None
 # per-job path's measured capacity at 200 jobs/s), resident-job slots and the
 # HBM admission budget (288 GB of HBM3E minus a reserve for the rest of the
 # process)
-SERVE_MIX = {"max_l3": 40, "n_traj_choices": (64, 128, 256), "n_step_choices": (500, 1000)}
+SERVE_MIX = {"max_l3": 96, "n_traj_choices": (64, 128, 256), "n_step_choices": (500, 1000),
+             "large_n_traj": (16, 32)}
 SERVE_SLOTS = 16
 SERVE_HBM_BUDGET = 256 * 1024 ** 3
 
@@ -72,28 +73,39 @@ def config4_jobs(n_traj: int = 256) -> list[JobSpec]:
     return out
 
 
-def serving_stream(n_jobs: int, rate_per_s: float, seed: int = 1, max_l3: int = 40,
-                   n_traj_choices=(64, 128, 256, 512), n_step_choices=(500, 1000, 2000)):
+def serving_stream(n_jobs: int, rate_per_s: float, seed: int = 1, max_l3: int = 96,
+                   n_traj_choices=(64, 128, 256), n_step_choices=(500, 1000),
+                   l2_choices=(24, 32, 48, 64, 96), l3_weights=None, large_n_traj=(16, 32)):
     """Poisson arrivals (mean rate_per_s) of jobs of random dimension, size,
     beta, l, N and n_t.  Returns [(arrival_time_s, JobSpec)].
 
-    Sizes: 2D L in {24, 32, 48, 64, 96}; 3D L in {16, 24, 32, max_l3}
-    (lattices held on chip); beta in {0.21, 0.2216546, 0.23}."""
+    2D: L uniform in l2_choices.  3D: L drawn with l3_weights (default: 16,
+    24, 32 at 30 % each and 48, 64, 96 at 5, 3 and 2 %), restricted to
+    L <= max_l3.  beta uniform in {0.21, 0.2216546, 0.23}.  n_t from
+    n_traj_choices, except 3D lattices of L >= 48 (streamed from HBM), which
+    take n_t from large_n_traj.  2D and on-chip 3D jobs store bit-packed 3D /
+    int8 2D spins; streamed jobs int8."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    if l3_weights is None:
+        l3_weights = {16: 0.30, 24: 0.30, 32: 0.30, 48: 0.05, 64: 0.03, 96: 0.02}
+    l3 = [L for L in l3_weights if L <= max_l3]
+    w3 = np.array([l3_weights[L] for L in l3], dtype=float)
+    w3 /= w3.sum()
     t = 0.0
     out = []
     for i in range(n_jobs):
         t += float(rng.exponential(1.0 / rate_per_s))
         dim = int(rng.integers(2, 4))
         if dim == 2:
-            L = int(rng.choice([24, 32, 48, 64, 96]))
+            L = int(rng.choice(l2_choices))
         else:
-            L = int(rng.choice([16, 24, 32, max_l3]))
+            L = int(rng.choice(l3, p=w3))
         beta = float(rng.choice([0.21, BETA_3D, 0.23]))
         l = int(rng.integers(0, L))
         n_step = int(rng.choice(n_step_choices))
-        n_traj = int(rng.choice(n_traj_choices))
+        streamed = dim == 3 and L >= 48
+        n_traj = int(rng.choice(large_n_traj if streamed else n_traj_choices))
+        fmt = EE_SPINS_INT8 if (dim == 2 or streamed) else EE_SPINS_BITPACKED
         out.append((t, JobSpec(dim=dim, lt=L, lx=L, ly=L if dim == 3 else 1, n=2, beta=beta, l=l,
-                               n_step=n_step, n_traj=n_traj, seed=1000 + i,
-                               spin_format=EE_SPINS_INT8 if dim == 2 else EE_SPINS_BITPACKED)))
+                               n_step=n_step, n_traj=n_traj, seed=1000 + i, spin_format=fmt)))
     return out

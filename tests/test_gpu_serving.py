@@ -23,8 +23,9 @@ def _gpu():
 
 
 def small_mix(n=14, seed=3):
-    stream = workloads.serving_stream(n, rate_per_s=1000.0, seed=seed, max_l3=16,
-                                      n_traj_choices=(16, 32, 64), n_step_choices=(20, 40, 80))
+    stream = workloads.serving_stream(n, rate_per_s=1000.0, seed=seed, max_l3=48,
+                                      n_traj_choices=(16, 32, 64), n_step_choices=(20, 40, 80),
+                                      l3_weights={16: 0.6, 48: 0.4}, large_n_traj=(2,))
     return serve.requests_from_stream(stream)
 
 
@@ -50,8 +51,9 @@ def test_results_identical_alone_and_in_the_mix():
         assert np.array_equal(req.work, w), req.spec
         assert req.result.dF == r.dF and req.result.dF_err == r.dF_err or (
             math.isnan(r.dF_err) and math.isnan(req.result.dF_err))
+    assert any(r.spec.dim == 3 and r.spec.lx == 48 for r in done)  # a streamed job took part
     # and the oracle agrees with a served job
-    req = done[0]
+    req = min(done, key=lambda r: r.spec.n_traj * r.spec.sites)
     s = req.spec
     I, _ = eo.run(eo.Job(s.dim, s.lt, s.lx, s.ly, s.n, s.beta, s.l, s.n_step, s.n_traj, s.seed, s.reverse), 20)
     assert np.array_equal(I, req.work)
