@@ -79,6 +79,64 @@ def serving_run(n_jobs: int, rate: float = 200.0) -> dict:
     return out
 
 
+def _time_batch(jobs, n_therm, launch, reps=2):
+    import torch
+    from paper_2304_03311_amd import ee
+    best = None
+    for _ in range(reps):
+        for j in jobs:
+            j.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ee.batch_run(jobs, n_therm, cfg=launch)
+        res = [j.estimate() for j in jobs]
+        dt = time.perf_counter() - t0
+        kms = ee.ee_batch_kernel_ms()
+        if best is None or dt < best[0]:
+            best = (dt, kms, res)
+    return best
+
+
+def _time_per_job(jobs, n_therm):
+    import torch
+    for j in jobs:
+        j.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in jobs:
+        j.thermalize(n_therm)
+        j.run_protocol()
+    res = [j.estimate() for j in jobs]
+    return time.perf_counter() - t0, res
+
+
+def configs_run() -> dict:
+    """The other job sets, each through the persistent batched path (tuned
+    launch shape) and through the per-job launch path."""
+    from paper_2304_03311_amd import autotune, ee, workloads
+    n_therm = workloads.N_THERM
+    sets = {"c1_2d_16x16": [workloads.config1_job()],
+            "c3_3d_32cube_bitpacked": [workloads.config3_job()],
+            "c4_24_uneven_jobs": workloads.config4_jobs()}
+    out = {}
+    for name, specs in sets.items():
+        launch = autotune.cached(specs, n_therm) or autotune.tune(specs, n_therm)
+        jobs = [ee.Job(s) for s in specs]
+        att = sum(s.n_traj * s.sites * (n_therm + s.n_step) for s in specs)
+        ops = sum(ops_per_attempt(s.dim) * s.n_traj * s.sites * (n_therm + s.n_step) for s in specs)
+        dt, kms, res = _time_batch(jobs, n_therm, launch)
+        dtp, _ = _time_per_job(jobs, n_therm)
+        out[name] = {"jobs": len(specs), "attempts": att, "batched_ms": dt * 1e3,
+                     "batched_attempts_per_ns": att / (dt * 1e9), "kernel_ms": kms,
+                     "alu_frac": ops / (kms * 1e-3) / PEAK_INT_LANE_OPS,
+                     "jobs_per_s": len(specs) / dt, "per_job_path_ms": dtp * 1e3,
+                     "per_job_path_attempts_per_ns": att / (dtp * 1e9),
+                     "dS_first": res[0].dS, "dS_err_first": res[0].dF_err, "launch": launch}
+        for j in jobs:
+            j.close()
+    return out
+
+
 def streaming_run() -> dict:
     """Throughput of the HBM-streaming path on the largest serving shape
     (3D 96^3, n = 2, 32 trajectories, N = 100 after 10 thermalisation sweeps)."""
@@ -113,6 +171,7 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency) measurement")
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--no-tune", action="store_true", help="library default launch shape instead of the tuner's")
+    ap.add_argument("--no-configs", action="store_true", help="skip the c1/c3/c4 job sets")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device-to-device once (HBM counter calibration)")
     args = ap.parse_args()
@@ -204,6 +263,8 @@ def main() -> int:
             j.estimate()
         torch.cuda.synchronize()
         out["per_job_path_attempts_per_ns"] = attempts_per_step / ((time.perf_counter() - t0) * 1e9)
+    if not args.no_configs:
+        out["configs"] = configs_run()
     if not args.no_serve:
         out["serving"] = serving_run(args.serve_jobs)
         out["streaming_path"] = streaming_run()
