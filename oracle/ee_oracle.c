@@ -36,7 +36,8 @@
  *                                       x == l -> ramped (intra + inter)
  *                                       x >  l -> (r, 1, y, x)
  *   Weights   integer, in units of beta/N: bulk N, ramped intra N-m,
- *             ramped inter m.  H/T = -(beta/N) sum_b w_b s_a s_b.
+ *             ramped inter m.  H/T = -(beta/N) sum_b w_b s_a s_b.  (With
+ *             subsets, below, N is replaced by S everywhere.)
  *   Colour    (t+y+x) mod 2; a sweep = colour 0 then colour 1.
  *   Accept    K = s_i * sum_b w_b s_nb; accept iff u <= U(K) with
  *             U(K) = 2^32-1 if beta*K <= 0, else
@@ -55,6 +56,11 @@
  *   Reverse   flag bit 0: start at lambda = 1 (geometry A(l+1)) and ramp
  *             to lambda = 0 (the paper's "direct" realisation, App. A
  *             direct/reverse equality).
+ *   Subsets   flag bit 1 (App. B, protocol 2): the Ly rows of the ramped
+ *             column are ramped one after the other, row y during steps
+ *             [y S, (y+1) S) with S = N / Ly; all weights are then in units
+ *             of beta/S (bulk S, intra S - m_y, inter m_y) and W = -(beta/S) I.
+ *             Without the flag S = N and every row has m_y = m.
  */
 #include <math.h>
 #include <stdint.h>
@@ -118,29 +124,33 @@ typedef struct {
   int l, N, n_traj;
   uint64_t seed;
   int reverse;
+  int subsets;     /* protocol 2 of App. B */
+  int S;           /* weight unit: beta/S (S = N, or N/Ly with subsets) */
   int64_t V;       /* sites per replica */
   int64_t nsites;  /* n * V */
   /* bonds */
   int64_t nb;
   int64_t *ba, *bb;
   int8_t *bk;
+  int32_t *by;     /* y of each bond (the ramped row it belongs to) */
   /* per-site adjacency in CSR form */
   int64_t *adj_off;
   int64_t *adj_nbr;
   int8_t *adj_kind;
+  int32_t *adj_y;
 } geom;
 
 static int64_t site_index(const geom* G, int r, int t, int y, int x) {
   return (((int64_t)r * G->lt + t) * G->ly + y) * G->lx + x;
 }
 
-static void add_bond(geom* G, int64_t a, int64_t b, int kind) {
-  G->ba[G->nb] = a; G->bb[G->nb] = b; G->bk[G->nb] = (int8_t)kind; G->nb++;
+static void add_bond(geom* G, int64_t a, int64_t b, int kind, int y) {
+  G->ba[G->nb] = a; G->bb[G->nb] = b; G->bk[G->nb] = (int8_t)kind; G->by[G->nb] = y; G->nb++;
 }
 
 static void geom_free(geom* G) {
-  free(G->ba); free(G->bb); free(G->bk);
-  free(G->adj_off); free(G->adj_nbr); free(G->adj_kind);
+  free(G->ba); free(G->bb); free(G->bk); free(G->by);
+  free(G->adj_off); free(G->adj_nbr); free(G->adj_kind); free(G->adj_y);
   memset(G, 0, sizeof(*G));
 }
 
@@ -153,34 +163,39 @@ static int geom_build(geom* G, int dim, int lt, int lx, int ly, int n, double be
   if (n < 2 || !(beta >= 0.0) || l < 0 || l >= lx || N < 1 || n_traj < 0) return EO_EINVAL;
   G->dim = dim; G->lt = lt; G->lx = lx; G->ly = ly; G->n = n; G->beta = beta;
   G->l = l; G->N = N; G->n_traj = n_traj; G->seed = seed; G->reverse = flags & 1;
+  G->subsets = (flags >> 1) & 1;
+  if (G->subsets && N % ly) return EO_EINVAL;
+  G->S = G->subsets ? N / ly : N;
   G->V = (int64_t)lt * ly * lx;
   G->nsites = (int64_t)n * G->V;
   int64_t maxb = G->nsites * dim + (int64_t)n * ly; /* ramped column adds one bond per (r,y) */
   G->ba = (int64_t*)malloc(sizeof(int64_t) * maxb);
   G->bb = (int64_t*)malloc(sizeof(int64_t) * maxb);
   G->bk = (int8_t*)malloc(maxb);
-  if (!G->ba || !G->bb || !G->bk) { geom_free(G); return EO_ENOMEM; }
+  G->by = (int32_t*)malloc(sizeof(int32_t) * maxb);
+  if (!G->ba || !G->bb || !G->bk || !G->by) { geom_free(G); return EO_ENOMEM; }
   for (int r = 0; r < n; ++r)
     for (int t = 0; t < lt; ++t)
       for (int y = 0; y < ly; ++y)
         for (int x = 0; x < lx; ++x) {
           int64_t s = site_index(G, r, t, y, x);
-          add_bond(G, s, site_index(G, r, t, y, (x + 1) % lx), BOND_BULK);          /* +x */
-          if (dim == 3) add_bond(G, s, site_index(G, r, t, (y + 1) % ly, x), BOND_BULK); /* +y */
-          if (t == 0 && x < l) {                                                   /* glued */
-            add_bond(G, s, site_index(G, (r + 1) % n, 1, y, x), BOND_BULK);
-          } else if (t == 0 && x == l) {                                           /* ramped */
-            add_bond(G, s, site_index(G, r, 1, y, x), BOND_INTRA);
-            add_bond(G, s, site_index(G, (r + 1) % n, 1, y, x), BOND_INTER);
-          } else {                                                                 /* +t */
-            add_bond(G, s, site_index(G, r, (t + 1) % lt, y, x), BOND_BULK);
+          add_bond(G, s, site_index(G, r, t, y, (x + 1) % lx), BOND_BULK, y);          /* +x */
+          if (dim == 3) add_bond(G, s, site_index(G, r, t, (y + 1) % ly, x), BOND_BULK, y); /* +y */
+          if (t == 0 && x < l) {                                                      /* glued */
+            add_bond(G, s, site_index(G, (r + 1) % n, 1, y, x), BOND_BULK, y);
+          } else if (t == 0 && x == l) {                                              /* ramped */
+            add_bond(G, s, site_index(G, r, 1, y, x), BOND_INTRA, y);
+            add_bond(G, s, site_index(G, (r + 1) % n, 1, y, x), BOND_INTER, y);
+          } else {                                                                    /* +t */
+            add_bond(G, s, site_index(G, r, (t + 1) % lt, y, x), BOND_BULK, y);
           }
         }
   /* adjacency */
   G->adj_off = (int64_t*)calloc((size_t)G->nsites + 1, sizeof(int64_t));
   G->adj_nbr = (int64_t*)malloc(sizeof(int64_t) * 2 * G->nb);
   G->adj_kind = (int8_t*)malloc(2 * G->nb);
-  if (!G->adj_off || !G->adj_nbr || !G->adj_kind) { geom_free(G); return EO_ENOMEM; }
+  G->adj_y = (int32_t*)malloc(sizeof(int32_t) * 2 * G->nb);
+  if (!G->adj_off || !G->adj_nbr || !G->adj_kind || !G->adj_y) { geom_free(G); return EO_ENOMEM; }
   for (int64_t b = 0; b < G->nb; ++b) { G->adj_off[G->ba[b] + 1]++; G->adj_off[G->bb[b] + 1]++; }
   for (int64_t s = 0; s < G->nsites; ++s) G->adj_off[s + 1] += G->adj_off[s];
   int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * G->nsites);
@@ -188,22 +203,30 @@ static int geom_build(geom* G, int dim, int lt, int lx, int ly, int n, double be
   memcpy(fill, G->adj_off, sizeof(int64_t) * G->nsites);
   for (int64_t b = 0; b < G->nb; ++b) {
     int64_t a = G->ba[b], c = G->bb[b];
-    G->adj_nbr[fill[a]] = c; G->adj_kind[fill[a]] = G->bk[b]; fill[a]++;
-    G->adj_nbr[fill[c]] = a; G->adj_kind[fill[c]] = G->bk[b]; fill[c]++;
+    G->adj_nbr[fill[a]] = c; G->adj_kind[fill[a]] = G->bk[b]; G->adj_y[fill[a]] = G->by[b]; fill[a]++;
+    G->adj_nbr[fill[c]] = a; G->adj_kind[fill[c]] = G->bk[b]; G->adj_y[fill[c]] = G->by[b]; fill[c]++;
   }
   free(fill);
   return EO_OK;
 }
 
-/* bond weight in units of beta/N at ramp position m (0..N) */
-static int64_t bond_weight(const geom* G, int kind, int m) {
-  if (kind == BOND_INTRA) return (int64_t)(G->N - m);
-  if (kind == BOND_INTER) return (int64_t)m;
-  return (int64_t)G->N;
+/* Ramp position of row y when the protocol stands at position pos (0..N):
+ * every row follows pos, or (subsets) row y moves during [y S, (y+1) S). */
+static int row_m(const geom* G, int y, int pos) {
+  if (!G->subsets) return pos;
+  int m = pos - y * G->S;
+  return m < 0 ? 0 : (m > G->S ? G->S : m);
 }
 
-/* ramp position after protocol step k (k = -1 is the starting point) */
-static int ramp_m(const geom* G, int k) {
+/* bond weight in units of beta/S at protocol position pos */
+static int64_t bond_weight(const geom* G, int kind, int y, int pos) {
+  if (kind == BOND_INTRA) return (int64_t)(G->S - row_m(G, y, pos));
+  if (kind == BOND_INTER) return (int64_t)row_m(G, y, pos);
+  return (int64_t)G->S;
+}
+
+/* protocol position after step k (k = -1 is the starting point) */
+static int ramp_pos(const geom* G, int k) {
   int forward = k + 1;
   return G->reverse ? G->N - forward : forward;
 }
@@ -238,8 +261,8 @@ static void init_spins(const geom* G, uint32_t j, int8_t* s) {
         }
 }
 
-/* One Metropolis sweep at ramp position m: colour 0 over all replicas, then colour 1. */
-static void sweep(const geom* G, int m, uint32_t g, uint32_t j, int8_t* s) {
+/* One Metropolis sweep at protocol position pos: colour 0 over all replicas, then colour 1. */
+static void sweep(const geom* G, int pos, uint32_t g, uint32_t j, int8_t* s) {
   for (int colour = 0; colour < 2; ++colour)
     for (int r = 0; r < G->n; ++r)
       for (int t = 0; t < G->lt; ++t)
@@ -249,25 +272,26 @@ static void sweep(const geom* G, int m, uint32_t g, uint32_t j, int8_t* s) {
             int64_t i = site_index(G, r, t, y, x);
             int64_t field = 0;
             for (int64_t e = G->adj_off[i]; e < G->adj_off[i + 1]; ++e)
-              field += bond_weight(G, G->adj_kind[e], m) * s[G->adj_nbr[e]];
+              field += bond_weight(G, G->adj_kind[e], G->adj_y[e], pos) * s[G->adj_nbr[e]];
             int64_t K = (int64_t)s[i] * field;
-            uint32_t U = eo_threshold(G->beta, K, G->N);
+            uint32_t U = eo_threshold(G->beta, K, G->S);
             uint32_t u = site_uniform(G, 1, g, j, r, t, y, x);
             if (u <= U) s[i] = (int8_t)(-s[i]);
           }
 }
 
-/* Integer energy in units of beta/N:  H/T = (beta/N) * energy_units. */
-static int64_t energy_units(const geom* G, int m, const int8_t* s) {
+/* Integer energy in units of beta/S:  H/T = (beta/S) * energy_units. */
+static int64_t energy_units(const geom* G, int pos, const int8_t* s) {
   int64_t e = 0;
-  for (int64_t b = 0; b < G->nb; ++b) e -= bond_weight(G, G->bk[b], m) * s[G->ba[b]] * s[G->bb[b]];
+  for (int64_t b = 0; b < G->nb; ++b)
+    e -= bond_weight(G, G->bk[b], G->by[b], pos) * s[G->ba[b]] * s[G->bb[b]];
   return e;
 }
 
 /*
  * Run trajectories j0 <= j < j1 of one job: initial state, n_therm sweeps at
  * the starting ramp position, then the N protocol sweeps.  I_out[j - j0]
- * receives I_j (W_j = -(beta/N) I_j).  spins_out (nullable) receives the
+ * receives I_j (W_j = -(beta/S) I_j).  spins_out (nullable) receives the
  * final +-1 spins in the order ((((j-j0)*n + r)*Lt + t)*Ly + y)*Lx + x.
  * If n_step_run < N only the first n_step_run protocol sweeps are run (a
  * partial protocol, used to check resumption).
@@ -287,11 +311,11 @@ int eo_run(int dim, int lt, int lx, int ly, int n, double beta, int l, int N, in
   for (int j = j0; j < j1; ++j) {
     init_spins(&G, (uint32_t)j, s);
     uint32_t g = 0;
-    int m0 = ramp_m(&G, -1);
+    int m0 = ramp_pos(&G, -1);
     for (int k = 0; k < n_therm; ++k) sweep(&G, m0, g++, (uint32_t)j, s);
-    int64_t work_units = 0; /* sum_k [E(m_{k+1}) - E(m_k)](phi_k), units of beta/N */
+    int64_t work_units = 0; /* sum_k [E(pos_{k+1}) - E(pos_k)](phi_k), units of beta/S */
     for (int k = 0; k < n_step_run; ++k) {
-      int m_now = ramp_m(&G, k - 1), m_next = ramp_m(&G, k);
+      int m_now = ramp_pos(&G, k - 1), m_next = ramp_pos(&G, k);
       work_units += energy_units(&G, m_next, s) - energy_units(&G, m_now, s);
       sweep(&G, m_next, g++, (uint32_t)j, s);
     }
@@ -313,11 +337,11 @@ int eo_count_ramped_bonds(int dim, int lt, int lx, int ly, int n, int l) {
   return c;
 }
 
-/* Integer energy (units of beta/N) of a +-1 configuration at ramp position m. */
-int eo_energy_units(int dim, int lt, int lx, int ly, int n, int l, int N, int m, const int8_t* s,
+/* Integer energy (units of beta/S) of a +-1 configuration at protocol position m. */
+int eo_energy_units(int dim, int lt, int lx, int ly, int n, int l, int N, int m, int flags, const int8_t* s,
                     int64_t* out) {
   geom G;
-  int rc = geom_build(&G, dim, lt, lx, ly, n, 1.0, l, N, 1, 0, 0);
+  int rc = geom_build(&G, dim, lt, lx, ly, n, 1.0, l, N, 1, 0, flags);
   if (rc) return rc;
   if (m < 0 || m > N) { geom_free(&G); return EO_EINVAL; }
   *out = energy_units(&G, m, s);

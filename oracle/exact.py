@@ -51,7 +51,7 @@ class Lattice:
 
 
 def bonds(lat: Lattice, glued_upto: int | None = None, ramp: bool = True):
-    """Bond list [(a, b, kind)] of the replica lattice.
+    """Bond list [(a, b, kind, y)] of the replica lattice (y: the row of the bond).
 
     ``glued_upto`` overrides l for the glued columns x < glued_upto; with
     ``ramp=False`` no column is ramped (a pure geometry A(glued_upto)).
@@ -63,16 +63,16 @@ def bonds(lat: Lattice, glued_upto: int | None = None, ramp: bool = True):
             for y in range(lat.ly):
                 for x in range(lat.lx):
                     s = lat.index(r, t, y, x)
-                    out.append((s, lat.index(r, t, y, (x + 1) % lat.lx), BULK))
+                    out.append((s, lat.index(r, t, y, (x + 1) % lat.lx), BULK, y))
                     if lat.dim == 3:
-                        out.append((s, lat.index(r, t, (y + 1) % lat.ly, x), BULK))
+                        out.append((s, lat.index(r, t, (y + 1) % lat.ly, x), BULK, y))
                     if t == 0 and x < l:
-                        out.append((s, lat.index((r + 1) % lat.n, 1, y, x), BULK))
+                        out.append((s, lat.index((r + 1) % lat.n, 1, y, x), BULK, y))
                     elif t == 0 and x == l and ramp:
-                        out.append((s, lat.index(r, 1, y, x), INTRA))
-                        out.append((s, lat.index((r + 1) % lat.n, 1, y, x), INTER))
+                        out.append((s, lat.index(r, 1, y, x), INTRA, y))
+                        out.append((s, lat.index((r + 1) % lat.n, 1, y, x), INTER, y))
                     else:
-                        out.append((s, lat.index(r, (t + 1) % lat.lt, y, x), BULK))
+                        out.append((s, lat.index(r, (t + 1) % lat.lt, y, x), BULK, y))
     return out
 
 
@@ -214,7 +214,7 @@ def _site_coords(lat: Lattice):
 
 
 def exact_protocol(lat: Lattice, beta: float, N: int, start: str = "equilibrium",
-                   n_therm: int = 0, reverse: bool = False):
+                   n_therm: int = 0, reverse: bool = False, subsets: bool = False):
     """Exact distribution of the integer work I over trajectories.
 
     start='equilibrium': phi_0 ~ pi at the starting ramp position.
@@ -226,6 +226,10 @@ def exact_protocol(lat: Lattice, beta: float, N: int, start: str = "equilibrium"
     then one sweep (colour 0, then colour 1, single-site Metropolis kernels
     with acceptance min(1, exp(-Delta H/T))) at the new position.
 
+    subsets=True is protocol 2 of App. B: the Ly rows of the ramped column
+    move one after the other, row y during steps [y S, (y+1) S), S = N/Ly,
+    with weights in units of beta/S (W = -(beta/S) I).
+
     Returns (values, probs): the support of I and its probabilities.
     """
     ns = lat.nsites
@@ -235,18 +239,23 @@ def exact_protocol(lat: Lattice, beta: float, N: int, start: str = "equilibrium"
     ba = np.array([x[0] for x in b])
     bb = np.array([x[1] for x in b])
     bk = np.array([x[2] for x in b])
+    by = np.array([x[3] for x in b])
     S = _all_spins(ns).astype(np.int64)
     nstates = 1 << ns
     pair = S[:, ba] * S[:, bb]  # [state, bond]
+    if subsets and N % lat.ly:
+        raise ValueError("protocol 2 needs N divisible by Ly")
+    unit = N // lat.ly if subsets else N  # weights in units of beta/unit
 
-    def wvec(m):
-        w = np.full(bk.shape, N, dtype=np.int64)
-        w[bk == INTRA] = N - m
-        w[bk == INTER] = m
+    def wvec(pos):
+        m = np.clip(pos - by * unit, 0, unit) if subsets else np.full(by.shape, pos)
+        w = np.full(bk.shape, unit, dtype=np.int64)
+        w[bk == INTRA] = (unit - m)[bk == INTRA]
+        w[bk == INTER] = m[bk == INTER]
         return w
 
     def energy_units(m):
-        return -(pair @ wvec(m))  # H/T = (beta/N) * energy_units
+        return -(pair @ wvec(m))  # H/T = (beta/unit) * energy_units
 
     def m_of(k):  # ramp position after step k (k=-1: start)
         return N - (k + 1) if reverse else k + 1
@@ -260,19 +269,19 @@ def exact_protocol(lat: Lattice, beta: float, N: int, start: str = "equilibrium"
         for c in (0, 1):
             for i in np.nonzero(colour == c)[0]:
                 flipped = idx ^ (1 << int(i))
-                dE = (E[flipped] - E) * (beta / N)
+                dE = (E[flipped] - E) * (beta / unit)
                 acc = np.minimum(1.0, np.exp(-dE))  # acceptance from each state
                 # P has shape [nI, nstates]
                 P = P * (1.0 - acc)[None, :] + (P * acc[None, :])[:, flipped]
         return P
 
     m0 = m_of(-1)
-    Dmax = 2 * lat.n * lat.ly
+    Dmax = 2 * lat.n * (1 if subsets else lat.ly)  # bound on |D_k|: the rows that move in one step
     nI = 2 * Dmax * N + 1
     off = Dmax * N
     P = np.zeros((nI, nstates))
     if start == "equilibrium":
-        e = -energy_units(m0) * (beta / N)
+        e = -energy_units(m0) * (beta / unit)
         p = np.exp(e - e.max())
         P[off] = p / p.sum()
     elif start == "hot":

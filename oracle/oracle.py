@@ -33,7 +33,7 @@ def lib() -> ctypes.CDLL:
         L.eo_run.restype = ctypes.c_int
         L.eo_count_ramped_bonds.argtypes = [ctypes.c_int] * 6
         L.eo_count_ramped_bonds.restype = ctypes.c_int
-        L.eo_energy_units.argtypes = [ctypes.c_int] * 8 + [ctypes.c_void_p, ctypes.c_void_p]
+        L.eo_energy_units.argtypes = [ctypes.c_int] * 9 + [ctypes.c_void_p, ctypes.c_void_p]
         L.eo_energy_units.restype = ctypes.c_int
         L.eo_estimate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
@@ -68,10 +68,20 @@ class Job:
     n_traj: int
     seed: int
     reverse: bool = False
+    subsets: bool = False  # protocol 2 of App. B: the Ly rows ramped one after the other
 
     @property
     def nsites(self) -> int:
         return self.n * self.lt * self.ly * self.lx
+
+    @property
+    def flags(self) -> int:
+        return (1 if self.reverse else 0) | (2 if self.subsets else 0)
+
+    @property
+    def S(self) -> int:
+        """Weight unit beta/S: S = N, or N/Ly for protocol 2."""
+        return self.n_step // self.ly if self.subsets else self.n_step
 
 
 def run(job: Job, n_therm: int, j0: int = 0, j1: int | None = None, n_step_run: int | None = None,
@@ -82,7 +92,7 @@ def run(job: Job, n_therm: int, j0: int = 0, j1: int | None = None, n_step_run: 
     I = np.zeros(max(j1 - j0, 0), dtype=np.int64)
     spins = np.zeros((max(j1 - j0, 0), job.nsites), dtype=np.int8) if want_spins else None
     rc = lib().eo_run(job.dim, job.lt, job.lx, job.ly, job.n, job.beta, job.l, job.n_step,
-                      job.n_traj, job.seed, 1 if job.reverse else 0, n_therm, j0, j1, n_step_run,
+                      job.n_traj, job.seed, job.flags, n_therm, j0, j1, n_step_run,
                       I.ctypes.data, spins.ctypes.data if spins is not None else None)
     if rc != 0:
         raise ValueError(f"eo_run failed ({rc}) for {job}")
@@ -96,7 +106,7 @@ def count_ramped_bonds(dim, lt, lx, ly, n, l) -> int:
 def energy_units(job: Job, m: int, spins: np.ndarray) -> int:
     s = np.ascontiguousarray(spins, dtype=np.int8)
     out = ctypes.c_int64()
-    rc = lib().eo_energy_units(job.dim, job.lt, job.lx, job.ly, job.n, job.l, job.n_step, m,
+    rc = lib().eo_energy_units(job.dim, job.lt, job.lx, job.ly, job.n, job.l, job.n_step, m, job.flags,
                                s.ctypes.data, ctypes.addressof(out))
     if rc != 0:
         raise ValueError(rc)

@@ -134,7 +134,7 @@ def test_energy_endpoints_are_geometries():
             s = rng.choice(np.array([-1, 1], dtype=np.int8), size=lat0.nsites)
             for m, glued in ((0, l), (5, l + 1)):
                 b = ex.bonds(lat0, glued_upto=glued, ramp=False)
-                e = -sum(int(s[a]) * int(s[c]) for a, c, _ in b) * 5
+                e = -sum(int(s[a]) * int(s[c]) for a, c, *_ in b) * 5
                 assert eo.energy_units(job, m, s) == e
 
 
@@ -357,12 +357,13 @@ def test_estimator_bounds_and_closed_forms():
 MUTATIONS = {
     "work sign": ("if (I_out) I_out[j - j0] = -work_units;", "if (I_out) I_out[j - j0] = work_units;"),
     "sweep at lambda_k": ("sweep(&G, m_next, g++, (uint32_t)j, s);", "sweep(&G, m_now, g++, (uint32_t)j, s);"),
-    "dropped inter bond": ("field += bond_weight(G, G->adj_kind[e], m) * s[G->adj_nbr[e]];",
-                           "field += (G->adj_kind[e] == BOND_INTER ? 0 : bond_weight(G, G->adj_kind[e], m)) * s[G->adj_nbr[e]];"),
-    "glue to r-1": ("add_bond(G, s, site_index(G, (r + 1) % n, 1, y, x), BOND_BULK);",
-                    "add_bond(G, s, site_index(G, (r + n - 1) % n, 1, y, x), BOND_BULK);"),
+    "dropped inter bond": ("field += bond_weight(G, G->adj_kind[e], G->adj_y[e], pos) * s[G->adj_nbr[e]];",
+                           "field += (G->adj_kind[e] == BOND_INTER ? 0 : bond_weight(G, G->adj_kind[e], G->adj_y[e], pos)) * s[G->adj_nbr[e]];"),
+    "glue to r-1": ("add_bond(G, s, site_index(G, (r + 1) % n, 1, y, x), BOND_BULK, y);",
+                    "add_bond(G, s, site_index(G, (r + n - 1) % n, 1, y, x), BOND_BULK, y);"),
     "threshold beta": ("double x = (2.0 * beta * (double)K) / (double)N;", "double x = (1.0 * beta * (double)K) / (double)N;"),
-    "intra weight": ("if (kind == BOND_INTRA) return (int64_t)(G->N - m);", "if (kind == BOND_INTRA) return (int64_t)(G->N - m + 1);"),
+    "intra weight": ("if (kind == BOND_INTRA) return (int64_t)(G->S - row_m(G, y, pos));",
+                     "if (kind == BOND_INTRA) return (int64_t)(G->S - row_m(G, y, pos) + 1);"),
     "work after sweep": ("work_units += energy_units(&G, m_next, s) - energy_units(&G, m_now, s);\n      sweep(&G, m_next, g++, (uint32_t)j, s);",
                          "sweep(&G, m_next, g++, (uint32_t)j, s);\n      work_units += energy_units(&G, m_next, s) - energy_units(&G, m_now, s);"),
 }
@@ -402,3 +403,53 @@ def test_planted_mistakes_are_caught(tmp_path):
 
         caught = any(_oracle_vs_exact(run, c, n_traj=20000) < 1e-6 for c in cases)
         assert caught, f"planted mistake '{name}' was not detected"
+
+
+# --------------------------------------------------------------------------
+# Protocol 2 (App. B): the rows of the ramped column moved one at a time
+# --------------------------------------------------------------------------
+
+def test_protocol2_exact_propagation_obeys_jarzynski():
+    lat = ex.Lattice(3, 2, 2, 2, 2, 0)
+    dF_exact = -(ex.log_z_bruteforce(lat, BC3, 2, 2) - ex.log_z_bruteforce(lat, BC3, 2, 0))
+    for N, rev in ((2, False), (2, True), (4, False)):
+        v, p = ex.exact_protocol(lat, BC3, N, subsets=True, reverse=rev)
+        S = N // lat.ly
+        want = -dF_exact if rev else dF_exact
+        assert -math.log(ex.jarzynski_average(v, p, BC3, S)) == pytest.approx(want, abs=2e-13)
+    # and it is a different protocol from protocol 1 (different work law)
+    v1, p1 = ex.exact_protocol(lat, BC3, 2)
+    v2, p2 = ex.exact_protocol(lat, BC3, 2, subsets=True)
+    assert not (len(v1) == len(v2) and np.allclose(p1, p2))
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+def test_oracle_protocol2_matches_exact_propagation(reverse):
+    lat = ex.Lattice(3, 2, 2, 2, 2, 1)
+    N, n_therm = 4, 2
+    v, p = ex.exact_protocol(lat, BC3, N, start="hot", n_therm=n_therm, reverse=reverse, subsets=True)
+    job = eo.Job(3, 2, 2, 2, 2, BC3, 1, N, 20000, 17, reverse, subsets=True)
+    I, _ = eo.run(job, n_therm)
+    assert _chi2_pvalue(I, v, p) > 1e-4
+
+
+def test_protocol2_in_2d_is_protocol1():
+    a = eo.Job(2, 8, 8, 1, 2, BC2, 3, 12, 6, 5)
+    b = eo.Job(2, 8, 8, 1, 2, BC2, 3, 12, 6, 5, subsets=True)
+    Ia, sa = eo.run(a, 4, want_spins=True)
+    Ib, sb = eo.run(b, 4, want_spins=True)
+    assert np.array_equal(Ia, Ib) and np.array_equal(sa, sb)
+
+
+def test_protocol2_work_is_energy_difference_and_needs_divisible_N():
+    job = eo.Job(3, 4, 4, 4, 2, BC3, 2, 8, 2, 9, False, subsets=True)
+    for k in range(job.n_step):
+        Ik, sk = eo.run(job, 3, n_step_run=k, want_spins=True)
+        Ik1, _ = eo.run(job, 3, n_step_run=k + 1)
+        for j in range(job.n_traj):
+            dE = eo.energy_units(job, k + 1, sk[j]) - eo.energy_units(job, k, sk[j])
+            assert Ik1[j] - Ik[j] == -dE
+            # only row k // S moves during step k: its 2n bonds change by one unit each
+            assert abs(dE) <= 2 * job.n
+    with pytest.raises(ValueError):
+        eo.run(eo.Job(3, 4, 4, 4, 2, BC3, 2, 6, 2, 9, False, subsets=True), 1)
