@@ -73,6 +73,13 @@ typedef enum {
                               column l (the paper's "direct" realisation,
                               App. A direct/reverse equality).  The estimate
                               is then Delta F = -log Z_n(l)/Z_n(l+1).       */
+#define EE_FLAG_SUBSETS 2u /* protocol 2 of App. B: the ly rows of the ramped
+                              column move one after the other, row y during
+                              steps [y S, (y+1) S) with S = n_step / ly
+                              (n_step must be divisible by ly).  Couplings
+                              are then in units of beta/S and
+                              W_j = -(beta/S) I_j.  Identical to the default
+                              protocol in 2D.                               */
 
 /*
  * Problem statement of one job, in the paper's terms (Sec. 3; Sec. 4 and 5
@@ -97,7 +104,8 @@ typedef struct {
 
 /*
  * Result of one job (App. A estimator; Sec. 2 for dS).
- *   dF      = -log( (1/n_t) sum_j exp(-W_j) ),  W_j = -(beta/N) I_j
+ *   dF      = -log( (1/n_t) sum_j exp(-W_j) ),  W_j = -(beta/S) I_j with
+ *             S = N (S = N/ly with EE_FLAG_SUBSETS)
  *   dS      = dF / (n-1)
  *   dF_err  delete-one jackknife standard error of dF (NaN if n_t < 2)
  *   w_mean, w_var  mean and population variance of W

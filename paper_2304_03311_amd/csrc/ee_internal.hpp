@@ -6,8 +6,9 @@
 //   [jobdev]     ee_jobdev descriptor (read by every kernel)
 //   [selfptr]    one pointer to the descriptor (a 1-entry job table)
 //   [result]     ee_result written by the estimator kernel
-//   [ramp_thr]   (N+1) x (8*dim) uint32 Metropolis thresholds of the ramped
-//                sites, indexed [m][fa][b][c]: fa = anti-aligned fixed
+//   [ramp_thr]   (S+1) x (8*dim) uint32 Metropolis thresholds of the ramped
+//                sites (S = N, or N/ly for the subset protocol), indexed
+//                [m][fa][b][c]: fa = anti-aligned fixed
 //                neighbours (0..2dim-1), b = intra partner anti-aligned,
 //                c = inter partner anti-aligned
 //   [work]       n_traj x int64 integer works I_j
@@ -37,7 +38,8 @@ struct alignas(256) JobDev {
   int32_t R;            // rows per replica = lt*ly
   int32_t traj_words;   // int8 words per trajectory = 2*n*R*G
   int32_t packed_words; // bit-packed words per trajectory = 2*n*R*ceil(H/32)
-  int32_t reserved0;
+  int32_t S;            // weight unit beta/S: N, or N/ly for the subset protocol
+  int32_t subsets;      // EE_FLAG_SUBSETS: rows of the ramped column moved one at a time
   uint32_t key0, key1;  // Philox key
   uint32_t thr_bulk[4]; // U for a = 0..dim-1 anti-aligned neighbours (bulk/glued sites)
   uint32_t reverse;     // EE_FLAG_REVERSE
@@ -82,8 +84,8 @@ int ee_k_sweep_kernel_ptr(int dim, const void** fn);
 int ee_k_queue_reset_ptr(const void** fn);
 int ee_k_estimate_ptr(const void** fn);
 int ee_k_max_lds_bytes();
-int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int m, int work,
-                             void* stream);
+int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos, int dpos,
+                             int work, void* stream);
 int ee_k_launch_stream_init(const ee::JobDev* job, int n_traj, int lanes, void* stream);
 int ee_k_launch_zero_work(const ee::JobDev* job, int n_traj, void* stream);
 }

@@ -62,7 +62,7 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
 
 // Per-job constants, held in scalar registers.
 struct JP {
-  int dim, n, lt, ly, l, N, H, G, R, traj_words, packed_row_words;
+  int dim, n, lt, ly, l, N, S, subsets, H, G, R, traj_words, packed_row_words;
   uint32_t key0, key1, thr0, thr1, thr2, reverse, spin_format;
   uint32_t mR, sR, mLy, sLy;
   const uint32_t* ramp;
@@ -74,6 +74,7 @@ __device__ __forceinline__ JP load_jp(const JobDev* J) {
   JP P;
   P.dim = uni(J->dim);
   P.n = uni(J->n); P.lt = uni(J->lt); P.ly = uni(J->ly); P.l = uni(J->l); P.N = uni(J->N);
+  P.S = uni(J->S); P.subsets = uni(J->subsets);
   P.H = uni(J->H); P.G = uni(J->G); P.R = uni(J->R); P.traj_words = uni(J->traj_words);
   P.packed_row_words = (P.H + 31) >> 5;
   P.key0 = uni(J->key0); P.key1 = uni(J->key1);
@@ -106,10 +107,21 @@ __device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) { re
 // FULL: lx/2 is a multiple of 4 (no pad bytes, x-neighbours by byte
 // alignment of two words).  UJ: the trajectory index is uniform per wave.
 // W: consecutive words per lane (2 needs FULL and an even word count).
+// Ramp position (0..S) of row y when the protocol stands at position pos
+// (0..N): every row follows pos, or (subset protocol) row y moves during
+// steps [y S, (y+1) S).
+__device__ __forceinline__ int row_m(const JP& P, int y, int pos) {
+  if (!P.subsets) return pos;
+  const int m = pos - y * P.S;
+  return m < 0 ? 0 : (m > P.S ? P.S : m);
+}
+
+// pos: protocol position of this sweep; dpos: pos minus the previous
+// position (+1 forward, -1 reverse, 0 while thermalising).
 template <int DIM, bool FULL, bool UJ, int W>
 __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t* __restrict__ L,
                                            const uint32_t* __restrict__ thr, const int c,
-                                           const uint32_t g, uint32_t j, const int m,
+                                           const uint32_t g, uint32_t j, const int pos, const int dpos,
                                            const bool work, int& dI) {
   static_assert(W == 1 || (W == 2 && FULL), "two words per lane need whole rows");
   if (UJ) j = __builtin_amdgcn_readfirstlane(j);
@@ -194,7 +206,8 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
         const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
         a[q] = a[q] - (Tcut ^ S[q]) + (Teff ^ S[q]);
         if (p == ramp_p && w + q == ramp_w) {
-          // ramped site x = l: K = s (N a_fix + (N-m) s_intra + m s_inter)
+          // ramped site x = l: K = s (S a_fix + (S-m) s_intra + m s_inter)
+          const int m = row_m(P, y, pos);
           const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
           const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
           const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
@@ -203,9 +216,10 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
           rmask[q] = 0xFFu << ramp_sh;
           rbit[q] = (uint32_t)(uu <= U) << ramp_sh;
           if (work) {
-            // the ramped site of colour 0 sees phi_k: D_k term = 2 (b - c)
-            const int d = 2 * ((int)bb - (int)cc);
-            dI += P.reverse ? -d : d;
+            // the ramped site of colour 0 sees phi_k: its bonds' weights moved
+            // by (m - m_prev), so the D_k term is (m - m_prev) 2 (b - c)
+            const int dm = m - row_m(P, y, pos - dpos);
+            dI += dm * 2 * ((int)bb - (int)cc);
           }
         }
       }
@@ -327,19 +341,20 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
 
   int dI = 0;
   uint32_t g = (uint32_t)g0;
-  const int m0 = P.reverse ? P.N : 0;
+  const int pos0 = P.reverse ? P.N : 0;
   for (int s = 0; s < n_therm; ++s, ++g) {
-    if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 0, g, j, m0, false, dI);
+    if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 0, g, j, pos0, 0, false, dI);
     __syncthreads();
-    if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 1, g, j, m0, false, dI);
+    if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 1, g, j, pos0, 0, false, dI);
     __syncthreads();
   }
   if (flags & ee::kFlagProto) {
+    const int dpos = P.reverse ? -1 : 1;
     for (int k = 0; k < P.N; ++k, ++g) {
-      const int m = P.reverse ? P.N - 1 - k : k + 1;
-      if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 0, g, j, m, true, dI);
+      const int pos = P.reverse ? P.N - 1 - k : k + 1;
+      if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 0, g, j, pos, dpos, true, dI);
       __syncthreads();
-      if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 1, g, j, m, false, dI);
+      if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 1, g, j, pos, dpos, false, dI);
       __syncthreads();
     }
     if (dI != 0) atomicAdd(&s_dI[slot], dI);
@@ -420,8 +435,8 @@ sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_un
 // integer work goes to HBM with 64-bit atomics.
 // ---------------------------------------------------------------------------
 template <int DIM, bool FULL, int W>
-__device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int lanes, int c, uint32_t g, int m,
-                                            bool work) {
+__device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int lanes, int c, uint32_t g, int pos,
+                                            int dpos, bool work) {
   const int lt_ = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t j = blockIdx.y;
   uint32_t* L = P.spins + (size_t)j * P.traj_words;
@@ -439,12 +454,12 @@ __device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int la
   ln.dt = (ln.nrg - ln.dr * P.R) / P.ly;
   ln.dy = ln.nrg - ln.dr * P.R - ln.dt * P.ly;
   int dI = 0;
-  if (lt_ < lanes && ln.row0 < ln.nrg) half_sweep<DIM, FULL, true, W>(P, ln, L, s_thr, c, g, j, m, work, dI);
+  if (lt_ < lanes && ln.row0 < ln.nrg) half_sweep<DIM, FULL, true, W>(P, ln, L, s_thr, c, g, j, pos, dpos, work, dI);
   if (dI != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.work[j]), (unsigned long long)(long long)dI);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
-stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int m, int work) {
+stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int pos, int dpos, int work) {
   __shared__ uint32_t s_thr[8];
   const JP P = load_jp(J);
   const int dim = uni(J->dim);
@@ -455,13 +470,13 @@ stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int m, int wo
   const bool two = words_per_lane(P, lanes) == 2;
   const bool full = (P.H & 3) == 0;
   if (dim == 3) {
-    if (two) stream_half<3, true, 2>(P, s_thr, lanes, c, g, m, work != 0);
-    else if (full) stream_half<3, true, 1>(P, s_thr, lanes, c, g, m, work != 0);
-    else stream_half<3, false, 1>(P, s_thr, lanes, c, g, m, work != 0);
+    if (two) stream_half<3, true, 2>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+    else if (full) stream_half<3, true, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+    else stream_half<3, false, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
   } else {
-    if (two) stream_half<2, true, 2>(P, s_thr, lanes, c, g, m, work != 0);
-    else if (full) stream_half<2, true, 1>(P, s_thr, lanes, c, g, m, work != 0);
-    else stream_half<2, false, 1>(P, s_thr, lanes, c, g, m, work != 0);
+    if (two) stream_half<2, true, 2>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+    else if (full) stream_half<2, true, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+    else stream_half<2, false, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
   }
 }
 
@@ -512,7 +527,7 @@ __global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* con
   const int n = J->n_traj;
   const int64_t* I = J->work;
   const double beta = J->beta;
-  const double N = (double)J->N;
+  const double N = (double)J->S;  // W_j = -(beta/S) I_j
   ee_result* res = J->result;
   double* scratch = reinterpret_cast<double*>(J->work + n);  // n doubles after the works
 
@@ -625,11 +640,11 @@ int ee_k_launch_sweep(int dim, const ee::JobDev* single_job, int single_k, const
   return (int)hipGetLastError();
 }
 
-int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int m, int work,
-                             void* stream) {
+int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos, int dpos,
+                             int work, void* stream) {
   const int bx = (lanes + 255) / 256;
   hipLaunchKernelGGL(stream_sweep_kernel, dim3(bx, n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c, g,
-                     m, work);
+                     pos, dpos, work);
   return (int)hipGetLastError();
 }
 

@@ -83,7 +83,9 @@ ee_status validate(const ee_job_desc* d) {
     return fail(EE_EINVAL, "n_traj must be in [1, 65535] (got %d)", d->n_traj);
   if (d->spin_format != EE_SPINS_INT8 && d->spin_format != EE_SPINS_BITPACKED)
     return fail(EE_EINVAL, "unknown spin_format %d", d->spin_format);
-  if (d->flags & ~EE_FLAG_REVERSE) return fail(EE_EINVAL, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(EE_FLAG_REVERSE | EE_FLAG_SUBSETS)) return fail(EE_EINVAL, "unknown flags 0x%x", d->flags);
+  if ((d->flags & EE_FLAG_SUBSETS) && d->n_step % d->ly)
+    return fail(EE_EINVAL, "the subset protocol needs n_step divisible by ly (%d %% %d)", d->n_step, d->ly);
   // |I| <= 2 n ly N must fit the int32 accumulators
   if (2.0 * d->n_replicas * d->ly * (double)d->n_step >= 2147483647.0)
     return fail(EE_EINVAL, "2*n*ly*n_step exceeds the int32 work range");
@@ -259,10 +261,11 @@ ee_status stream_sweeps(ee_job* j, int n_sweeps, bool protocol) {
   uint32_t g = (uint32_t)j->g;
   const int N = j->d.n_step;
   const bool rev = (j->d.flags & EE_FLAG_REVERSE) != 0;
+  const int dpos = protocol ? (rev ? -1 : 1) : 0;
   for (int s = 0; s < n_sweeps && rc == 0; ++s, ++g) {
-    const int m = protocol ? (rev ? N - 1 - s : s + 1) : (rev ? N : 0);
-    rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 0, g, m, protocol ? 1 : 0, j->stream);
-    if (rc == 0) rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 1, g, m, 0, j->stream);
+    const int pos = protocol ? (rev ? N - 1 - s : s + 1) : (rev ? N : 0);
+    rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 0, g, pos, dpos, protocol ? 1 : 0, j->stream);
+    if (rc == 0) rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 1, g, pos, dpos, 0, j->stream);
   }
   if (rc) return fail(EE_EHIP, "streaming sweep launch failed: %s", hipGetErrorString((hipError_t)rc));
   return EE_OK;
@@ -472,6 +475,8 @@ ee_status ee_job_create(const ee_job_desc* desc, void* dev_arena, size_t arena_b
   j->cfg = ee_launch_cfg{0, 0, 0, 1, 0};
   j->streaming = j->L.traj_words * 4 > ee_k_max_lds_bytes();
   const int dim = desc->dim, N = desc->n_step;
+  const bool subsets = (desc->flags & EE_FLAG_SUBSETS) != 0;
+  const int S = subsets ? N / desc->ly : N;  // weights in units of beta/S
   // thresholds
   ee::JobDev& D = j->host_jobdev;
   std::memset(&D, 0, sizeof(D));
@@ -481,7 +486,9 @@ ee_status ee_job_create(const ee_job_desc* desc, void* dev_arena, size_t arena_b
   D.packed_words = j->L.packed_words;
   D.key0 = (uint32_t)(desc->seed & 0xFFFFFFFFu);
   D.key1 = (uint32_t)(desc->seed >> 32);
-  for (int a = 0; a < dim; ++a) D.thr_bulk[a] = threshold(desc->beta, (int64_t)N * (2 * dim - 2 * a), N);
+  D.S = S;
+  D.subsets = subsets ? 1 : 0;
+  for (int a = 0; a < dim; ++a) D.thr_bulk[a] = threshold(desc->beta, (int64_t)S * (2 * dim - 2 * a), S);
   D.reverse = (desc->flags & EE_FLAG_REVERSE) ? 1u : 0u;
   D.spin_format = (uint32_t)desc->spin_format;
   ee::Magic mr = ee::make_magic((uint32_t)j->L.R), my = ee::make_magic((uint32_t)desc->ly);
@@ -491,15 +498,15 @@ ee_status ee_job_create(const ee_job_desc* desc, void* dev_arena, size_t arena_b
   D.spins = reinterpret_cast<uint32_t*>(j->arena + j->L.off_spins);
   D.work = reinterpret_cast<int64_t*>(j->arena + j->L.off_work);
   D.result = j->dev_result();
-  // ramped-site thresholds U_m[fa][b][c], K = N(2dim-1-2fa) + (N-m)(1-2b) + m(1-2c)
-  j->host_ramp.resize((size_t)(N + 1) * 8 * dim);
-  for (int m = 0; m <= N; ++m)
+  // ramped-site thresholds U_m[fa][b][c], K = S(2dim-1-2fa) + (S-m)(1-2b) + m(1-2c)
+  j->host_ramp.resize((size_t)(S + 1) * 8 * dim);
+  for (int m = 0; m <= S; ++m)
     for (int fa = 0; fa < 2 * dim; ++fa)
       for (int b = 0; b < 2; ++b)
         for (int c = 0; c < 2; ++c) {
-          const int64_t K = (int64_t)N * (2 * dim - 1 - 2 * fa) + (int64_t)(N - m) * (1 - 2 * b) +
+          const int64_t K = (int64_t)S * (2 * dim - 1 - 2 * fa) + (int64_t)(S - m) * (1 - 2 * b) +
                             (int64_t)m * (1 - 2 * c);
-          j->host_ramp[(size_t)m * 8 * dim + fa * 4 + b * 2 + c] = threshold(desc->beta, K, N);
+          j->host_ramp[(size_t)m * 8 * dim + fa * 4 + b * 2 + c] = threshold(desc->beta, K, S);
         }
   j->host_selfptr = j->dev_jobdev();
   hipError_t e = hipMemcpyAsync(j->dev_jobdev(), &j->host_jobdev, sizeof(ee::JobDev), hipMemcpyHostToDevice, j->stream);

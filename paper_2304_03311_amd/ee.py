@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libee.so")
 EE_OK, EE_EINVAL, EE_ENOMEM, EE_EHIP, EE_ESTATE, EE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 EE_SPINS_INT8, EE_SPINS_BITPACKED = 0, 1
 EE_FLAG_REVERSE = 1
+EE_FLAG_SUBSETS = 2
 EE_LAUNCH_STREAMING = 1
 
 
@@ -199,10 +200,17 @@ class JobSpec:
     seed: int
     spin_format: int = EE_SPINS_INT8
     reverse: bool = False
+    subsets: bool = False  # protocol 2 of App. B
 
     def desc(self) -> ee_job_desc:
+        flags = (EE_FLAG_REVERSE if self.reverse else 0) | (EE_FLAG_SUBSETS if self.subsets else 0)
         return make_desc(self.dim, self.lt, self.lx, self.ly, self.n, self.beta, self.l, self.n_step,
-                         self.n_traj, self.seed, self.spin_format, EE_FLAG_REVERSE if self.reverse else 0)
+                         self.n_traj, self.seed, self.spin_format, flags)
+
+    @property
+    def S(self) -> int:
+        """Coupling unit beta/S: N, or N/ly for the subset protocol."""
+        return self.n_step // self.ly if self.subsets else self.n_step
 
     @property
     def sites(self) -> int:

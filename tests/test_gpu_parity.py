@@ -42,12 +42,12 @@ def df_tol(est: eo.Estimate, beta: float, N: int, n_t: int) -> float:
 
 
 def oracle_job(s: ee.JobSpec) -> eo.Job:
-    return eo.Job(s.dim, s.lt, s.lx, s.ly, s.n, s.beta, s.l, s.n_step, s.n_traj, s.seed, s.reverse)
+    return eo.Job(s.dim, s.lt, s.lx, s.ly, s.n, s.beta, s.l, s.n_step, s.n_traj, s.seed, s.reverse, s.subsets)
 
 
 def check_estimate(res: ee.ee_result, I: np.ndarray, s: ee.JobSpec):
-    est = eo.estimate(I, s.beta, s.n_step, s.n)
-    tol = df_tol(est, s.beta, s.n_step, s.n_traj)
+    est = eo.estimate(I, s.beta, s.S, s.n)
+    tol = df_tol(est, s.beta, s.S, s.n_traj)
     assert abs(res.dF - est.dF) <= tol, (res.dF, est.dF, tol)
     assert abs(res.dS - est.dS) <= tol
     assert res.i_min == est.i_min and res.i_max == est.i_max
@@ -80,6 +80,13 @@ CASES = [
     ("3d_bitpacked_reverse", dict(dim=3, lt=6, lx=10, ly=4, n=2, beta=0.25, l=4, n_step=8, n_traj=4, seed=14,
                                   spin_format=1, reverse=True), 5),
     ("3d_n3", dict(dim=3, lt=4, lx=8, ly=4, n=3, beta=BC3, l=0, n_step=6, n_traj=3, seed=15), 3),
+    ("3d_protocol2", dict(dim=3, lt=6, lx=8, ly=4, n=2, beta=BC3, l=3, n_step=12, n_traj=5, seed=16, subsets=True), 4),
+    ("3d_protocol2_reverse", dict(dim=3, lt=4, lx=16, ly=6, n=2, beta=0.23, l=9, n_step=18, n_traj=4, seed=17,
+                                  subsets=True, reverse=True), 3),
+    ("3d_protocol2_bitpacked", dict(dim=3, lt=4, lx=6, ly=2, n=3, beta=0.3, l=5, n_step=4, n_traj=3, seed=18,
+                                    subsets=True, spin_format=1), 3),
+    ("2d_protocol2_is_protocol1", dict(dim=2, lt=8, lx=16, ly=1, n=2, beta=BC2, l=4, n_step=9, n_traj=4, seed=19,
+                                       subsets=True), 3),
 ]
 
 
@@ -119,6 +126,7 @@ def test_initial_and_thermalised_spins_match_oracle(name, kw, n_therm):
 
 def test_batch_path_matches_per_job_and_oracle():
     specs = [ee.JobSpec(**kw) for _, kw, _ in CASES if kw["dim"] == 2][:8]
+    specs += [ee.JobSpec(**kw) for name, kw, _ in CASES if name.startswith("3d_protocol2")]
     n_therm = 6
     say(f"[gpu] batch of {len(specs)} uneven 2D jobs")
     jobs = [ee.Job(s) for s in specs]

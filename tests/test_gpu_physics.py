@@ -72,6 +72,17 @@ def test_3d_increments_match_transfer_matrix():
         check(r, exact_dF(3, lt, lx, ly, 2, l, BC3), n_t)
 
 
+def test_3d_protocol2_matches_transfer_matrix():
+    """Protocol 2 of App. B (rows moved one at a time) estimates the same
+    Delta F as protocol 1."""
+    lt, lx, ly, n_t, N = 4, 2, 2, 4096, 32
+    specs = [ee.JobSpec(dim=3, lt=lt, lx=lx, ly=ly, n=2, beta=BC3, l=l, n_step=N, n_traj=n_t, seed=70 + l,
+                        subsets=True) for l in range(lx)]
+    res = run_jobs(specs, 200)
+    for l, r in enumerate(res):
+        check(r, exact_dF(3, lt, lx, ly, 2, l, BC3), n_t)
+
+
 def test_direct_and_reverse_protocols_agree():
     """<e^-W>_dir = 1/<e^-W>_rev (App. A): dF_forward = -dF_reverse."""
     kw = dict(dim=2, lt=32, lx=16, ly=1, n=2, beta=BC2, l=5, n_step=200, n_traj=2048)
