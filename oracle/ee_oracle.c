@@ -42,15 +42,23 @@
  *   Accept    K = s_i * sum_b w_b s_nb; accept iff u <= U(K) with
  *             U(K) = 2^32-1 if beta*K <= 0, else
  *             max(floor(2^32 exp(-(2 beta K)/N)), 1) - 1, evaluated in
- *             FP64 exactly as (2.0*beta*(double)K)/(double)N.
+ *             FP64 exactly as (2.0*beta*(double)K)/(double)N, and u a
+ *             uniform 32-bit integer u = 2^16 v + w (below).
  *   RNG       Philox4x32-10 (Salmon et al., SC'11), key = (seed lo, seed
  *             hi).  Site with colour c, half-index h = x>>1, row rho =
- *             t*Ly+y, G = ceil((Lx/2)/4) groups per row:
- *               counter = (rho*G + (h>>2), g, j, (phase<<28)|(r<<1)|c),
- *               u = output word (h & 3).
- *             phase 0 (g = 0): initial spin +1 iff u < 2^31.
- *             phase 1: sweep number g (thermalisation sweeps first, then
- *             the protocol sweeps), counted per job.
+ *             t*Ly+y.
+ *             Initial spin (phase 0, g = 0): with G4 = ceil((Lx/2)/4),
+ *               counter = (rho*G4 + (h>>2), 0, j, (r<<1)|c), +1 iff output
+ *               word (h & 3) < 2^31.
+ *             Sweep g (thermalisation sweeps first, then the protocol):
+ *             with G8 = ceil((Lx/2)/8), one call serves the 8 sites of a
+ *             row with the same h>>3:
+ *               counter = (rho*G8 + (h>>3), g, j, (phase<<28)|(r<<1)|c),
+ *               field(phase) = 16-bit half (h & 1) (low half first) of
+ *               output word ((h & 7) >> 1);
+ *             v = field(1); w = field(2) is drawn only when v = U >> 16,
+ *             the only case in which u <= U depends on it.  So u is uniform
+ *             on [0, 2^32) and P(accept) = (U+1)/2^32 exactly.
  *   Work      D_k = sum over ramped bonds of (w(m_{k+1}) - w(m_k)) s s,
  *             I = sum_k D_k, W = -(beta/N) I   (exact integer).
  *   Reverse   flag bit 0: start at lambda = 1 (geometry A(l+1)) and ramp
@@ -234,18 +242,41 @@ static int ramp_pos(const geom* G, int k) {
 /* ------------------------------------------------------------------ */
 /* Random numbers of one site                                          */
 /* ------------------------------------------------------------------ */
-static uint32_t site_uniform(const geom* G, uint32_t phase, uint32_t g, uint32_t j, int r, int t,
-                             int y, int x) {
+static void site_philox(const geom* G, int group_size, uint32_t phase, uint32_t g, uint32_t j, int r, int t,
+                        int y, int x, uint32_t out[4]) {
   int c = (t + y + x) & 1;
   int h = x >> 1;
-  int groups = (G->lx / 2 + 3) / 4;
+  int groups = (G->lx / 2 + group_size - 1) / group_size;
   int rho = t * G->ly + y;
-  uint32_t ctr[4] = {(uint32_t)(rho * groups + (h >> 2)), g, j,
+  uint32_t ctr[4] = {(uint32_t)(rho * groups + h / group_size), g, j,
                      (phase << 28) | ((uint32_t)r << 1) | (uint32_t)c};
   uint32_t key[2] = {(uint32_t)(G->seed & 0xFFFFFFFFu), (uint32_t)(G->seed >> 32)};
-  uint32_t out[4];
   eo_philox4x32_10(ctr, key, out);
-  return out[h & 3];
+}
+
+/* uniform 32-bit word of the initial spin (4 sites per call) */
+static uint32_t init_uniform(const geom* G, uint32_t j, int r, int t, int y, int x) {
+  uint32_t out[4];
+  site_philox(G, 4, 0, 0, j, r, t, y, x, out);
+  return out[(x >> 1) & 3];
+}
+
+/* 16-bit field of a sweep's random numbers (8 sites per call) */
+static uint32_t sweep_field(const geom* G, uint32_t phase, uint32_t g, uint32_t j, int r, int t, int y, int x) {
+  uint32_t out[4];
+  site_philox(G, 8, phase, g, j, r, t, y, x, out);
+  int h = x >> 1;
+  uint32_t word = out[(h & 7) >> 1];
+  return (h & 1) ? (word >> 16) : (word & 0xFFFFu);
+}
+
+/* Metropolis decision u <= U with u = 2^16 v + w uniform on [0, 2^32) */
+static int accept(const geom* G, uint32_t U, uint32_t g, uint32_t j, int r, int t, int y, int x) {
+  uint32_t v = sweep_field(G, 1, g, j, r, t, y, x);
+  uint32_t u_hi = U >> 16;
+  if (v != u_hi) return v < u_hi;
+  uint32_t w = sweep_field(G, 2, g, j, r, t, y, x);
+  return w <= (U & 0xFFFFu);
 }
 
 /* ------------------------------------------------------------------ */
@@ -256,7 +287,7 @@ static void init_spins(const geom* G, uint32_t j, int8_t* s) {
     for (int t = 0; t < G->lt; ++t)
       for (int y = 0; y < G->ly; ++y)
         for (int x = 0; x < G->lx; ++x) {
-          uint32_t u = site_uniform(G, 0, 0, j, r, t, y, x);
+          uint32_t u = init_uniform(G, j, r, t, y, x);
           s[site_index(G, r, t, y, x)] = (u < 0x80000000u) ? 1 : -1;
         }
 }
@@ -275,8 +306,7 @@ static void sweep(const geom* G, int pos, uint32_t g, uint32_t j, int8_t* s) {
               field += bond_weight(G, G->adj_kind[e], G->adj_y[e], pos) * s[G->adj_nbr[e]];
             int64_t K = (int64_t)s[i] * field;
             uint32_t U = eo_threshold(G->beta, K, G->S);
-            uint32_t u = site_uniform(G, 1, g, j, r, t, y, x);
-            if (u <= U) s[i] = (int8_t)(-s[i]);
+            if (accept(G, U, g, j, r, t, y, x)) s[i] = (int8_t)(-s[i]);
           }
 }
 
@@ -323,6 +353,20 @@ int eo_run(int dim, int lt, int lx, int ly, int n, double beta, int l, int N, in
     if (spins_out) memcpy(spins_out + (int64_t)(j - j0) * G.nsites, s, (size_t)G.nsites);
   }
   free(s);
+  geom_free(&G);
+  return EO_OK;
+}
+
+/* The two 16-bit fields (v, w) of one site in sweep g and the lazy
+ * decision for threshold U (test hook for the decision rule). */
+int eo_site_fields(int dim, int lt, int lx, int ly, int n, uint64_t seed, uint32_t g, uint32_t j, int r, int t,
+                   int y, int x, uint32_t U, uint32_t* v, uint32_t* w, int* decision) {
+  geom G;
+  int rc = geom_build(&G, dim, lt, lx, ly, n, 1.0, 0, 1, 1, seed, 0);
+  if (rc) return rc;
+  *v = sweep_field(&G, 1, g, j, r, t, y, x);
+  *w = sweep_field(&G, 2, g, j, r, t, y, x);
+  *decision = accept(&G, U, g, j, r, t, y, x);
   geom_free(&G);
   return EO_OK;
 }

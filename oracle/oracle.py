@@ -38,6 +38,9 @@ def lib() -> ctypes.CDLL:
         L.eo_estimate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         L.eo_estimate.restype = ctypes.c_int
+        L.eo_site_fields.argtypes = [ctypes.c_int] * 5 + [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32] + [
+            ctypes.c_int] * 4 + [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.eo_site_fields.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -97,6 +100,17 @@ def run(job: Job, n_therm: int, j0: int = 0, j1: int | None = None, n_step_run: 
     if rc != 0:
         raise ValueError(f"eo_run failed ({rc}) for {job}")
     return I, spins
+
+
+def site_fields(dim, lt, lx, ly, n, seed, g, j, r, t, y, x, U):
+    """(v, w, decision) of one site in sweep g: the two 16-bit fields and the
+    oracle's lazy Metropolis decision for threshold U."""
+    v, w, d = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int()
+    rc = lib().eo_site_fields(dim, lt, lx, ly, n, seed, g, j, r, t, y, x, U, ctypes.byref(v), ctypes.byref(w),
+                              ctypes.byref(d))
+    if rc != 0:
+        raise ValueError(rc)
+    return int(v.value), int(w.value), int(d.value)
 
 
 def count_ramped_bonds(dim, lt, lx, ly, n, l) -> int:

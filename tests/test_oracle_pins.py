@@ -77,6 +77,35 @@ def test_philox_counter_words_all_matter():
     assert eo.philox((1, 2, 3, 4), (5, 7)) != base
 
 
+def test_lazy_decision_equals_32bit_comparison():
+    """Accepting on the 16-bit field v and drawing w only on a tie is the
+    same decision as u <= U with u = 2^16 v + w."""
+    rng = np.random.default_rng(5)
+    for _ in range(400):
+        t, y, x = int(rng.integers(0, 8)), int(rng.integers(0, 4)), int(rng.integers(0, 12))
+        g, j, r = int(rng.integers(0, 1000)), int(rng.integers(0, 50)), int(rng.integers(0, 2))
+        v, w, _ = eo.site_fields(3, 8, 12, 4, 2, 99, g, j, r, t, y, x, 0)
+        for U in (0, 0xFFFFFFFF, int(rng.integers(0, 2**32)), (v << 16) | w, ((v << 16) | w) - 1,
+                  (v << 16) | 0xFFFF, (v << 16), ((v + 1) << 16) & 0xFFFFFFFF):
+            U &= 0xFFFFFFFF
+            _, _, d = eo.site_fields(3, 8, 12, 4, 2, 99, g, j, r, t, y, x, U)
+            assert d == int(((v << 16) | w) <= U), (v, w, U)
+
+
+def test_sweep_fields_are_philox_halves():
+    """v and w are 16-bit halves of Philox4x32-10 words (phases 1 and 2, one
+    call per 8 sites of a row)."""
+    for (t, y, x) in [(0, 0, 0), (3, 1, 7), (5, 2, 23), (7, 3, 16)]:
+        c, h = (t + y + x) & 1, x >> 1
+        G8 = (24 // 2 + 7) // 8
+        for phase in (1, 2):
+            out = eo.philox(((t * 4 + y) * G8 + (h >> 3), 17, 3, (phase << 28) | (1 << 1) | c), (99, 0))
+            word = out[(h & 7) >> 1]
+            want = (word >> 16) if (h & 1) else (word & 0xFFFF)
+            v, w, _ = eo.site_fields(3, 8, 24, 4, 2, 99, 17, 3, 1, t, y, x, 0)
+            assert (v, w)[phase - 1] == want
+
+
 # --------------------------------------------------------------------------
 # Thresholds
 # --------------------------------------------------------------------------
