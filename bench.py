@@ -41,13 +41,15 @@ def kernel_hash() -> str:
 def ops_per_attempt(dim: int) -> float:
     """Algorithmic VALU lane-instructions per Metropolis attempt on gfx950.
 
-    The minimal instruction sequence of the method: a quarter of one
+    The minimal instruction sequence of the method: an eighth of one
     Philox4x32-10 call (10 rounds of 2 v_mad_u64_u32 and 2 three-input xor =
-    40 per call, 4 uniforms) = 10, plus, per 32-bit word of 4 same-colour
-    sites, 2*dim xor-add of the anti-aligned neighbour counts, 1 byte-align
-    for the x neighbours, 3 per site for the acceptance (extract, compare,
-    select) and 1 xor to apply the flips."""
-    return 10.0 + (2 * dim + 1 + 3 * 4 + 1) / 4.0
+    40 per call, eight 16-bit fields) = 5, plus, per 32-bit word of 4
+    same-colour sites: 2*dim xor-add of the anti-aligned neighbour counts,
+    1 byte-align for the x neighbours, 1 shift and 4 extracts for the
+    threshold-table offsets, 4 differences v - (U >> 16), 2 permutes, 1 or
+    and 1 shift to gather the flip bytes, 1 masked xor to apply them and 2
+    three-input minima for the tie test."""
+    return 5.0 + (2 * dim + 1 + 1 + 4 + 4 + 2 + 1 + 1 + 1 + 2) / 4.0
 
 
 def cpu_baseline(n_traj_sample: int) -> dict:

@@ -5,11 +5,12 @@
 //   (int8 spins, colour-separated rows) and runs, entirely on chip, the
 //   initial spins, the thermalisation sweeps and the N protocol sweeps with
 //   the integer work (Sec. 3 linear protocol; App. A work-then-update).
-//   One lane updates one 32-bit word = 4 same-colour sites of a row with one
-//   Philox4x32-10 call (one 32-bit uniform per site) and an integer compare
-//   against a uint32 threshold per site.  In batch mode the workgroups are
-//   persistent and pull work units (job, block of trajectories) from a
-//   device queue.
+//   One lane updates W 32-bit words = 4W same-colour sites of a row.  One
+//   Philox4x32-10 call gives a 16-bit field to each of 8 sites; a site
+//   accepts when its field is below the top half of its uint32 threshold,
+//   and only a tie (probability 2^-16) draws the low 16 bits from a second
+//   call.  In batch mode the workgroups are persistent and pull work units
+//   (job, block of trajectories) from a device queue.
 // estimate_kernel: Jarzynski estimator of one job per workgroup (App. A):
 //   integer max/min/sum of I_j, FP64 sum of exp(beta (I_j - I_max)/N),
 //   log-sum-exp, delete-one jackknife from prefix/suffix sums.
@@ -62,7 +63,7 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
 
 // Per-job constants, held in scalar registers.
 struct JP {
-  int dim, n, lt, ly, l, N, S, subsets, H, G, R, traj_words, packed_row_words;
+  int dim, n, lt, ly, l, N, S, subsets, H, G, G8, R, traj_words, packed_row_words;
   uint32_t key0, key1, thr0, thr1, thr2, reverse, spin_format;
   uint32_t mR, sR, mLy, sLy;
   const uint32_t* ramp;
@@ -76,6 +77,7 @@ __device__ __forceinline__ JP load_jp(const JobDev* J) {
   P.n = uni(J->n); P.lt = uni(J->lt); P.ly = uni(J->ly); P.l = uni(J->l); P.N = uni(J->N);
   P.S = uni(J->S); P.subsets = uni(J->subsets);
   P.H = uni(J->H); P.G = uni(J->G); P.R = uni(J->R); P.traj_words = uni(J->traj_words);
+  P.G8 = (P.H + 7) >> 3;
   P.packed_row_words = (P.H + 31) >> 5;
   P.key0 = uni(J->key0); P.key1 = uni(J->key1);
   P.thr0 = uni(J->thr_bulk[0]); P.thr1 = uni(J->thr_bulk[1]); P.thr2 = uni(J->thr_bulk[2]);
@@ -114,6 +116,24 @@ __device__ __forceinline__ int row_m(const JP& P, int y, int pos) {
   if (!P.subsets) return pos;
   const int m = pos - y * P.S;
   return m < 0 ? 0 : (m > P.S ? P.S : m);
+}
+
+// 16-bit half hi (0 low, 1 high) of a Philox output word.
+__device__ __forceinline__ uint32_t half16(uint32_t word, int hi) { return hi ? (word >> 16) : (word & 0xFFFFu); }
+
+// Row (in the lane's own trajectory) of the glued partner across the cut of
+// row (r, t, y), t in {0, 1}: replica r+1 at t = 1 for t = 0, replica r-1 at
+// t = 0 for t = 1.
+__device__ __forceinline__ int glued_row(const JP& P, int r, int t, int y) {
+  const int rgl = (t == 0) ? ((r + 1 == P.n) ? 0 : r + 1) : ((r == 0) ? P.n - 1 : r - 1);
+  return rgl * P.R + (1 - t) * P.ly + y;
+}
+
+// Byte mask of the glued sites (x < l) of a word whose first site has
+// x = l - v: bytes i with 2i < v.
+__device__ __forceinline__ uint32_t glued_mask(int v) {
+  const int ng = (v <= 0) ? 0 : ((v + 1) >> 1);
+  return (ng >= 4) ? 0xFFFFFFFFu : ((1u << (8 * ng)) - 1u);
 }
 
 // pos: protocol position of this sweep; dpos: pos minus the previous
@@ -181,63 +201,105 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
 #pragma unroll
       for (int q = 0; q < W; ++q) a[q] = xad(Lo[oym + q], S[q], xad(Lo[oyp + q], S[q], a[q]));
     }
-    uint32_t u[W][4];
-    const uint32_t c0 = (uint32_t)((row - r * P.R) * G + w);
-    const uint32_t c3 = ctr3 | ((uint32_t)r << 1);
-#pragma unroll
-    for (int q = 0; q < W; ++q) philox10(c0 + q, g, j, c3, P.key0, P.key1, u[q]);
-    uint32_t rmask[W], rbit[W];
-#pragma unroll
-    for (int q = 0; q < W; ++q) rmask[q] = rbit[q] = 0;
     if (t <= 1) {
       // Row next to the cut: for glued columns x < l the temporal partner
       // across the cut is in replica r+1 (t = 0) or r-1 (t = 1).
-      const int rgl = (t == 0) ? ((r + 1 == P.n) ? 0 : r + 1) : ((r == 0) ? P.n - 1 : r - 1);
-      const int og = (rgl * P.R + (1 - t) * P.ly + y) * G + w;
+      const int og = glued_row(P, r, t, y) * G + w;
       const uint32_t t0mask = (t == 0) ? 0xFFFFFFFFu : 0u;
 #pragma unroll
       for (int q = 0; q < W; ++q) {
         const uint32_t Tg = Lo[og + q];
-        const int v = P.l - p - 8 * (w + q);  // bytes i with 8(w+q) + 2i + p < l are glued
-        const int ng = (v <= 0) ? 0 : ((v + 1) >> 1);
-        const uint32_t gm = (ng >= 4) ? 0xFFFFFFFFu : ((1u << (8 * ng)) - 1u);
+        const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
         // own-replica partner across the cut: Tp on t = 0, Tm on t = 1
         const uint32_t Tcut = (Tp[q] & t0mask) | (Tm[q] & ~t0mask);
         const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
         a[q] = a[q] - (Tcut ^ S[q]) + (Teff ^ S[q]);
-        if (p == ramp_p && w + q == ramp_w) {
-          // ramped site x = l: K = s (S a_fix + (S-m) s_intra + m s_inter)
-          const int m = row_m(P, y, pos);
-          const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
-          const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
-          const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
-          const uint32_t U = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
-          const uint32_t uu = (ramp_sh == 0) ? u[q][0] : (ramp_sh == 8) ? u[q][1] : (ramp_sh == 16) ? u[q][2] : u[q][3];
-          rmask[q] = 0xFFu << ramp_sh;
-          rbit[q] = (uint32_t)(uu <= U) << ramp_sh;
-          if (work) {
-            // the ramped site of colour 0 sees phi_k: its bonds' weights moved
-            // by (m - m_prev), so the D_k term is (m - m_prev) 2 (b - c)
-            const int dm = m - row_m(P, y, pos - dpos);
-            dI += dm * 2 * ((int)bb - (int)cc);
-          }
-        }
       }
     }
+    // Random numbers: one Philox call serves the 8 sites of this row with the
+    // same h >> 3; site i of word q uses the 16-bit half (i & 1) of output
+    // word ob + 2q + (i >> 1).  The decision u <= U with u = 2^16 v + w is
+    // v < U >> 16 unless v equals U >> 16; only then is w (a phase-2 call)
+    // needed.  d = v - (U >> 16) in 32 bits: its sign bit is the first
+    // decision and d == 0 marks a tie.
+    uint32_t u[4];
+    const uint32_t c0 = (uint32_t)((row - r * P.R) * P.G8 + (w >> 1));
+    const uint32_t c3 = ctr3 | ((uint32_t)r << 1);
+    philox10(c0, g, j, c3, P.key0, P.key1, u);
+    const int ob = (W == 1) ? 2 * (w & 1) : 0;
+    uint32_t f[W];
+    uint32_t dmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int q = 0; q < W; ++q) {
-      // acceptance: u <= thr[a] per site; the table offset is 4a = byte i of (a << 2)
+      // bulk/glued sites: threshold thr[a] from the LDS table (offset 4a = byte i of a << 2)
       const uint32_t a4 = a[q] << 2;
-      uint32_t f = 0;
+      uint32_t d[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
                                                                ((a4 >> (8 * i)) & 0xFFu));
-        f |= (uint32_t)(u[q][i] <= th) << (8 * i);
+        d[i] = half16(u[ob + 2 * q + (i >> 1)], i & 1) - (th >> 16);
+        dmin = min(dmin, d[i]);
       }
-      f = ((f & ~rmask[q]) | rbit[q]) & valid;
-      Lc[rowbase + w + q] = S[q] ^ f;
+      // byte i <- byte 3 of d[i]; its top bit moved to bit 0 is the flip
+      const uint32_t lo = __builtin_amdgcn_perm(d[1], d[0], 0x0c0c0703u);
+      const uint32_t hi = __builtin_amdgcn_perm(d[3], d[2], 0x07030c0cu);
+      f[q] = ((lo | hi) >> 7) & 0x01010101u;
     }
+    if (__builtin_expect(dmin == 0, 0)) {
+      // rare (2^-16 per site): decide the tied sites on u = 2^16 v + w
+      uint32_t u2[4];
+      philox10(c0, g, j, c3 + (1u << 28), P.key0, P.key1, u2);
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        const uint32_t a4 = a[q] << 2;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
+                                                                 ((a4 >> (8 * i)) & 0xFFu));
+          if (half16(u[ob + 2 * q + (i >> 1)], i & 1) == (th >> 16)) {
+            const uint32_t acc = half16(u2[ob + 2 * q + (i >> 1)], i & 1) <= (th & 0xFFFFu);
+            f[q] = (f[q] & ~(0xFFu << (8 * i))) | (acc << (8 * i));
+          }
+        }
+      }
+    }
+    if (t <= 1 && p == ramp_p && (unsigned)(ramp_w - w) < (unsigned)W) {
+      // ramped site x = l of a row next to the cut (one lane per row): its
+      // threshold replaces the bulk decision taken above for its byte.
+      // K = s (S a_fix + (S-m) s_intra + m s_inter) in units of beta/S.
+      const int og = glued_row(P, r, t, y) * G + w;
+      const int m = row_m(P, y, pos);
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        if (w + q != ramp_w) continue;
+        const uint32_t Tg = Lo[og + q];
+        const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
+        const uint32_t Tcut = (t == 0) ? Tp[q] : Tm[q];
+        const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
+        const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
+        const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
+        const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
+        const uint32_t Ur = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
+        const int ri = ramp_sh >> 3;
+        const uint32_t vr = half16(u[ob + 2 * q + (ri >> 1)], ri & 1);
+        uint32_t acc = vr < (Ur >> 16);
+        if (vr == (Ur >> 16)) {
+          uint32_t u2[4];
+          philox10(c0, g, j, c3 + (1u << 28), P.key0, P.key1, u2);
+          acc = half16(u2[ob + 2 * q + (ri >> 1)], ri & 1) <= (Ur & 0xFFFFu);
+        }
+        f[q] = (f[q] & ~(0xFFu << ramp_sh)) | (acc << ramp_sh);
+        if (work) {
+          // the ramped site of colour 0 sees phi_k: its bonds' weights moved
+          // by (m - m_prev), so the D_k term is (m - m_prev) 2 (b - c)
+          const int dm = m - row_m(P, y, pos - dpos);
+          dI += dm * 2 * ((int)bb - (int)cc);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < W; ++q) Lc[rowbase + w + q] = S[q] ^ (f[q] & valid);
     // next row of this lane
     if (DIM == 3) {
       y += ln.dy;
