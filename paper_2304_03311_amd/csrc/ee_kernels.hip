@@ -61,10 +61,32 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+// Philox4x32-10 whose output words 0 and 2 come xored with m: those words
+// are the three-input xors of the last round, so m joins its (uniform) key
+// at no cost.
+__device__ __forceinline__ void philox10_x02(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1, uint32_t m, uint32_t out[4]) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, (i == 9) ? (k0 ^ m) : k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, (i == 9) ? (k1 ^ m) : k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
 // Per-job constants, held in scalar registers.
 struct JP {
   int dim, n, lt, ly, l, N, S, subsets, H, G, G8, R, traj_words, packed_row_words;
   uint32_t key0, key1, thr0, thr1, thr2, reverse, spin_format;
+  uint32_t pt_hi0, pt_hi1, pt_lo0, pt_lo1;  // byte tables of (thr[a] >> 16) ^ 0x8000, a = 0..7
   uint32_t mR, sR, mLy, sLy;
   const uint32_t* ramp;
   uint32_t* spins;
@@ -82,6 +104,23 @@ __device__ __forceinline__ JP load_jp(const JobDev* J) {
   P.key0 = uni(J->key0); P.key1 = uni(J->key1);
   P.thr0 = uni(J->thr_bulk[0]); P.thr1 = uni(J->thr_bulk[1]); P.thr2 = uni(J->thr_bulk[2]);
   P.reverse = uni(J->reverse); P.spin_format = uni(J->spin_format);
+  // Top halves of the bulk thresholds thr[a] (a anti-aligned neighbours;
+  // 2^32-1 for a >= dim), offset by 0x8000 so that the unsigned order of
+  // 16-bit fields becomes the signed order, as high and low byte tables
+  // indexed by a through v_perm_b32 (a <= 7).
+  P.pt_hi0 = P.pt_hi1 = P.pt_lo0 = P.pt_lo1 = 0;
+  for (int a = 0; a < 8; ++a) {
+    const uint32_t th = (a == 0) ? P.thr0 : (a == 1) ? P.thr1 : (a == 2 && P.dim == 3) ? P.thr2 : 0xFFFFFFFFu;
+    const uint32_t t16 = (th >> 16) ^ 0x8000u;
+    const uint32_t sh = 8u * (uint32_t)(a & 3);
+    if (a < 4) {
+      P.pt_hi0 |= (t16 >> 8) << sh;
+      P.pt_lo0 |= (t16 & 0xFFu) << sh;
+    } else {
+      P.pt_hi1 |= (t16 >> 8) << sh;
+      P.pt_lo1 |= (t16 & 0xFFu) << sh;
+    }
+  }
   P.mR = uni(J->magic_R); P.sR = uni(J->shift_R); P.mLy = uni(J->magic_Ly); P.sLy = uni(J->shift_Ly);
   P.ramp = uni_ptr(J->ramp_thr);
   P.spins = uni_ptr(J->spins);
@@ -108,7 +147,8 @@ __device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) { re
 //        anti-aligned neighbours (2^32-1 for a >= DIM)
 // FULL: lx/2 is a multiple of 4 (no pad bytes, x-neighbours by byte
 // alignment of two words).  UJ: the trajectory index is uniform per wave.
-// W: consecutive words per lane (2 needs FULL and an even word count).
+// W: consecutive words per lane (2 or 4 need FULL and a word count that W
+// divides).
 // Ramp position (0..S) of row y when the protocol stands at position pos
 // (0..N): every row follows pos, or (subset protocol) row y moves during
 // steps [y S, (y+1) S).
@@ -116,6 +156,27 @@ __device__ __forceinline__ int row_m(const JP& P, int y, int pos) {
   if (!P.subsets) return pos;
   const int m = pos - y * P.S;
   return m < 0 ? 0 : (m > P.S ? P.S : m);
+}
+
+// Output word o (0..3, possibly not a compile-time constant) of a Philox
+// result, by selects rather than a dynamically indexed register array.
+__device__ __forceinline__ uint32_t pick4(const uint32_t u[4], int o) {
+  const uint32_t lo = (o & 1) ? u[1] : u[0];
+  const uint32_t hi = (o & 1) ? u[3] : u[2];
+  return (o & 2) ? hi : lo;
+}
+
+// Two 16-bit lanes per 32-bit word: saturating signed difference a - b, and
+// unsigned minimum (v_pk_sub_i16 with clamp, v_pk_min_u16).
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t sub_sat_s16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(s16x2, a),
+                                                                    __builtin_bit_cast(s16x2, b)));
+}
+__device__ __forceinline__ uint32_t min_u16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
 }
 
 // 16-bit half hi (0 low, 1 high) of a Philox output word.
@@ -143,7 +204,8 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
                                            const uint32_t* __restrict__ thr, const int c,
                                            const uint32_t g, uint32_t j, const int pos, const int dpos,
                                            const bool work, int& dI) {
-  static_assert(W == 1 || (W == 2 && FULL), "two words per lane need whole rows");
+  static_assert(W == 1 || ((W == 2 || W == 4) && FULL), "several words per lane need whole rows");
+  constexpr int NC = (W + 1) / 2;  // Philox calls per row: 8 sites each
   if (UJ) j = __builtin_amdgcn_readfirstlane(j);
   const int G = P.G;
   const int cw = P.n * P.R * G;  // words per colour plane
@@ -151,7 +213,7 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
   const uint32_t* __restrict__ Lo = L + (c ^ 1) * cw;
   const int nrows = P.n * P.R;
   const int LyG = P.ly * G;
-  const int twrap = (P.lt - 1) * LyG;
+  const int ltLyG = P.lt * LyG;
   const int ywrap = (P.ly - 1) * G;
   const uint32_t ctr3 = (1u << 28) | (uint32_t)c;
   const int ramp_w = P.l >> 3;
@@ -160,6 +222,7 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
   const int w = ln.w;
   const int tailsh = 8 * ((P.H - 1) & 3);
   const uint32_t valid = (!FULL && w == G - 1 && tailsh != 24) ? ((1u << (tailsh + 8)) - 1u) : 0xFFFFFFFFu;
+  const uint32_t fmask = valid & 0x01010101u;  // bit 0 of every real site's byte
   const uint32_t rshift = (w == G - 1) ? (uint32_t)tailsh : 24u;
   int r = ln.r0, t = ln.t0, y = ln.y0;
   int rowbase = ln.row0 * G;
@@ -185,8 +248,9 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
       const uint32_t Bl = (A[0] << 8) | ((w == 0) ? ((nb >> tailsh) & 0xFFu) : (nb >> 24));
       B[0] = p ? Br : Bl;
     }
-    const int om = rowbase + ((t == 0) ? twrap : -LyG) + w;
-    const int op = rowbase + ((t == P.lt - 1) ? -twrap : LyG) + w;
+    // t -+ 1 neighbours; the periodic wrap adds or removes one replica's rows
+    const int om = rowbase + w - LyG + ((t == 0) ? ltLyG : 0);
+    const int op = rowbase + w + LyG - ((t == P.lt - 1) ? ltLyG : 0);
     uint32_t Tm[W], Tp[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) {
@@ -220,46 +284,58 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
     // same h >> 3; site i of word q uses the 16-bit half (i & 1) of output
     // word ob + 2q + (i >> 1).  The decision u <= U with u = 2^16 v + w is
     // v < U >> 16 unless v equals U >> 16; only then is w (a phase-2 call)
-    // needed.  d = v - (U >> 16) in 32 bits: its sign bit is the first
-    // decision and d == 0 marks a tie.
-    uint32_t u[4];
+    // needed.  Sites 0, 1 of word q take the halves of one output word and
+    // sites 2, 3 those of the next, so both sides are compared two at a time
+    // as 16-bit lanes: d = sat(v' - t) with v' = v ^ 0x8000 and
+    // t = (U >> 16) ^ 0x8000 has the sign of v - (U >> 16), and d = 0 marks
+    // a tie.
+    // Call k serves words 2k and 2k+1 of the lane (W >= 2) or, with W = 1,
+    // the lane's word alone, whose fields start at output word ob.
     const uint32_t c0 = (uint32_t)((row - r * P.R) * P.G8 + (w >> 1));
     const uint32_t c3 = ctr3 | ((uint32_t)r << 1);
-    philox10(c0, g, j, c3, P.key0, P.key1, u);
     const int ob = (W == 1) ? 2 * (w & 1) : 0;
     uint32_t f[W];
     uint32_t dmin = 0xFFFFFFFFu;
 #pragma unroll
-    for (int q = 0; q < W; ++q) {
-      // bulk/glued sites: threshold thr[a] from the LDS table (offset 4a = byte i of a << 2)
-      const uint32_t a4 = a[q] << 2;
-      uint32_t d[4];
+    for (int k = 0; k < NC; ++k) {
+      // u[0], u[2] arrive as v ^ 0x8000 per field; u[1], u[3] are xored here
+      uint32_t u[4];
+      philox10_x02(c0 + k, g, j, c3, P.key0, P.key1, 0x80008000u, u);
+      u[1] ^= 0x80008000u;
+      u[3] ^= 0x80008000u;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
-                                                               ((a4 >> (8 * i)) & 0xFFu));
-        d[i] = half16(u[ob + 2 * q + (i >> 1)], i & 1) - (th >> 16);
-        dmin = min(dmin, d[i]);
+      for (int q = 2 * k; q < 2 * k + 2 && q < W; ++q) {
+        // bulk/glued sites: t of site i from the byte tables, selected by byte i of a
+        const uint32_t th = __builtin_amdgcn_perm(P.pt_hi1, P.pt_hi0, a[q]);
+        const uint32_t tl = __builtin_amdgcn_perm(P.pt_lo1, P.pt_lo0, a[q]);
+        const int o = (ob + 2 * q) & 3;
+        const uint32_t d01 = sub_sat_s16x2(pick4(u, o), __builtin_amdgcn_perm(th, tl, 0x05010400u));
+        const uint32_t d23 = sub_sat_s16x2(pick4(u, o + 1), __builtin_amdgcn_perm(th, tl, 0x07030602u));
+        dmin = min_u16x2(dmin, min_u16x2(d01, d23));
+        // byte i <- the high byte of site i's difference: its bit 7 is the flip
+        f[q] = __builtin_amdgcn_perm(d23, d01, 0x07050301u);
       }
-      // byte i <- byte 3 of d[i]; its top bit moved to bit 0 is the flip
-      const uint32_t lo = __builtin_amdgcn_perm(d[1], d[0], 0x0c0c0703u);
-      const uint32_t hi = __builtin_amdgcn_perm(d[3], d[2], 0x07030c0cu);
-      f[q] = ((lo | hi) >> 7) & 0x01010101u;
     }
-    if (__builtin_expect(dmin == 0, 0)) {
-      // rare (2^-16 per site): decide the tied sites on u = 2^16 v + w
-      uint32_t u2[4];
-      philox10(c0, g, j, c3 + (1u << 28), P.key0, P.key1, u2);
+    if (__builtin_expect(((dmin & 0xFFFFu) == 0) | ((dmin >> 16) == 0), 0)) {
+      // rare (2^-16 per site): decide the tied sites on u = 2^16 v + w; the
+      // phase-1 fields are drawn again rather than kept in registers
 #pragma unroll
-      for (int q = 0; q < W; ++q) {
-        const uint32_t a4 = a[q] << 2;
+      for (int k = 0; k < NC; ++k) {
+        uint32_t u1[4], u2[4];
+        philox10(c0 + k, g, j, c3, P.key0, P.key1, u1);
+        philox10(c0 + k, g, j, c3 + (1u << 28), P.key0, P.key1, u2);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
-                                                                 ((a4 >> (8 * i)) & 0xFFu));
-          if (half16(u[ob + 2 * q + (i >> 1)], i & 1) == (th >> 16)) {
-            const uint32_t acc = half16(u2[ob + 2 * q + (i >> 1)], i & 1) <= (th & 0xFFFFu);
-            f[q] = (f[q] & ~(0xFFu << (8 * i))) | (acc << (8 * i));
+        for (int q = 2 * k; q < 2 * k + 2 && q < W; ++q) {
+          const uint32_t a4 = a[q] << 2;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
+                                                                   ((a4 >> (8 * i)) & 0xFFu));
+            const int o = ((ob + 2 * q) & 3) + (i >> 1);
+            if (half16(pick4(u1, o), i & 1) == (th >> 16)) {
+              const uint32_t acc = half16(pick4(u2, o), i & 1) <= (th & 0xFFFFu);
+              f[q] = (f[q] & ~(0xFFu << (8 * i))) | (acc << (8 * i + 7));
+            }
           }
         }
       }
@@ -269,27 +345,31 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
       // threshold replaces the bulk decision taken above for its byte.
       // K = s (S a_fix + (S-m) s_intra + m s_inter) in units of beta/S.
       const int og = glued_row(P, r, t, y) * G + w;
+      const int oc = rowbase + ((t == 0) ? LyG : -LyG) + w;  // own-replica partner across the cut
       const int m = row_m(P, y, pos);
 #pragma unroll
       for (int q = 0; q < W; ++q) {
         if (w + q != ramp_w) continue;
         const uint32_t Tg = Lo[og + q];
+        const uint32_t Tcut = Lo[oc + q];
         const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
-        const uint32_t Tcut = (t == 0) ? Tp[q] : Tm[q];
         const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
         const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
         const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
         const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
         const uint32_t Ur = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
         const int ri = ramp_sh >> 3;
-        const uint32_t vr = half16(u[ob + 2 * q + (ri >> 1)], ri & 1);
+        const int o = ((ob + 2 * q) & 3) + (ri >> 1);
+        uint32_t u1[4];
+        philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
+        const uint32_t vr = half16(pick4(u1, o), ri & 1);
         uint32_t acc = vr < (Ur >> 16);
         if (vr == (Ur >> 16)) {
           uint32_t u2[4];
-          philox10(c0, g, j, c3 + (1u << 28), P.key0, P.key1, u2);
-          acc = half16(u2[ob + 2 * q + (ri >> 1)], ri & 1) <= (Ur & 0xFFFFu);
+          philox10(c0 + (q >> 1), g, j, c3 + (1u << 28), P.key0, P.key1, u2);
+          acc = half16(pick4(u2, o), ri & 1) <= (Ur & 0xFFFFu);
         }
-        f[q] = (f[q] & ~(0xFFu << ramp_sh)) | (acc << ramp_sh);
+        f[q] = (f[q] & ~(0xFFu << ramp_sh)) | (acc << (ramp_sh + 7));
         if (work) {
           // the ramped site of colour 0 sees phi_k: its bonds' weights moved
           // by (m - m_prev), so the D_k term is (m - m_prev) 2 (b - c)
@@ -299,7 +379,10 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
       }
     }
 #pragma unroll
-    for (int q = 0; q < W; ++q) Lc[rowbase + w + q] = S[q] ^ (f[q] & valid);
+    for (int q = 0; q < W; ++q) {
+      // S ^ ((f >> 7) & fmask) in one three-input op (table 0x78 = a ^ (b & c))
+      Lc[rowbase + w + q] = __builtin_amdgcn_bitop3_b32(S[q], f[q] >> 7, fmask, 0x78);
+    }
     // next row of this lane
     if (DIM == 3) {
       y += ln.dy;
@@ -427,22 +510,31 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
   __syncthreads();
 }
 
-// Words per lane for a job and slot size: two when rows are whole words in
-// pairs and every row still gets a lane group.
-__device__ __forceinline__ int words_per_lane(const JP& P, int T) {
+// Words per lane for a job and slot size of T lanes: the widest W <= wmax
+// (4 or 2) that divides the row's words and still gives every row a lane
+// group.
+__device__ __forceinline__ int words_per_lane(const JP& P, int T, int wmax) {
+  if (wmax >= 4 && (P.H & 15) == 0 && T / (P.G / 4) >= 1) return 4;
   return ((P.H & 7) == 0 && T / (P.G / 2) >= 1) ? 2 : 1;
 }
 
-template <int DIM>
+template <int DIM, int WMAX>
 __device__ __forceinline__ void run_unit_dispatch(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr,
                                                   int j0, int cnt, int kslots, uint32_t flags, int n_therm,
                                                   int g0) {
   const int T = blockDim.x / kslots;
   const bool full = (P.H & 3) == 0;
   const bool uj = (T & 63) == 0;
-  const bool two = words_per_lane(P, T) == 2;
-  if (two && uj) run_unit<DIM, true, true, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else if (two) run_unit<DIM, true, false, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  const int wpl = words_per_lane(P, T, WMAX);
+  if constexpr (WMAX >= 4) {
+    if (wpl == 4) {
+      if (uj) run_unit<DIM, true, true, 4>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      else run_unit<DIM, true, false, 4>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      return;
+    }
+  }
+  if (wpl == 2 && uj) run_unit<DIM, true, true, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else if (wpl == 2) run_unit<DIM, true, false, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
   else if (full && uj) run_unit<DIM, true, true, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
   else if (full) run_unit<DIM, true, false, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
   else run_unit<DIM, false, false, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
@@ -452,9 +544,11 @@ __device__ __forceinline__ void run_unit_dispatch(const JP& P, uint32_t* lds, in
 // [b*single_k, b*single_k + single_k) of single_job.  Batch mode: persistent
 // workgroups draw units from the queue until it is empty.  The dimension of
 // each unit's job selects the 2D or 3D sweep (uniform per workgroup).
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
-sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_units, int* queue,
-             const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0) {
+// WMAX: the widest lane (words per lane) the entry point compiles.
+template <int WMAX>
+__device__ __forceinline__ void sweep_body(const JobDev* single_job, int single_k, const Unit* units, int n_units,
+                                           int* queue, const JobDev* const* jobtab, uint32_t flags, int n_therm,
+                                           int g0) {
   extern __shared__ uint32_t lds[];
   __shared__ int s_unit;
   __shared__ int s_dI[ee::kMaxSlots];
@@ -482,10 +576,26 @@ sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_un
     }
     const JP P = load_jp(J);
     if (uni(J->dim) == 3)
-      run_unit_dispatch<3>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      run_unit_dispatch<3, WMAX>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
     else
-      run_unit_dispatch<2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      run_unit_dispatch<2, WMAX>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
   }
+}
+
+// Up to 8 waves per SIMD (64 VGPRs), one or two words per lane.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
+sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_units, int* queue,
+             const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0) {
+  sweep_body<2>(single_job, single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
+}
+
+// Up to 4 waves per SIMD (128 VGPRs) and up to four words per lane: the
+// per-row address and loop work is spread over 16 sites.  For launches
+// whose LDS use already holds a CU to 4 waves per SIMD or fewer.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
+sweep_kernel_wide(const JobDev* single_job, int single_k, const Unit* units, int n_units, int* queue,
+                  const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0) {
+  sweep_body<4>(single_job, single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
 }
 
 // ---------------------------------------------------------------------------
@@ -529,7 +639,7 @@ stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int pos, int 
     s_thr[threadIdx.x] = (threadIdx.x == 0) ? P.thr0 : (threadIdx.x == 1) ? P.thr1
                        : (threadIdx.x == 2 && dim == 3) ? P.thr2 : 0xFFFFFFFFu;
   __syncthreads();
-  const bool two = words_per_lane(P, lanes) == 2;
+  const bool two = words_per_lane(P, lanes, 2) == 2;
   const bool full = (P.H & 3) == 0;
   if (dim == 3) {
     if (two) stream_half<3, true, 2>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
@@ -677,8 +787,8 @@ static hipError_t set_lds_attr(const void* fn) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, ee_k_max_lds_bytes());
 }
 
-int ee_k_sweep_kernel_ptr(int /*dim*/, const void** fn) {
-  *fn = reinterpret_cast<const void*>(&sweep_kernel);
+int ee_k_sweep_kernel_ptr(int wide, const void** fn) {
+  *fn = wide ? reinterpret_cast<const void*>(&sweep_kernel_wide) : reinterpret_cast<const void*>(&sweep_kernel);
   return (int)set_lds_attr(*fn);
 }
 int ee_k_queue_reset_ptr(const void** fn) {
@@ -690,15 +800,18 @@ int ee_k_estimate_ptr(const void** fn) {
   return 0;
 }
 
-int ee_k_launch_sweep(int dim, const ee::JobDev* single_job, int single_k, const ee::Unit* units,
+int ee_k_launch_sweep(int wide, const ee::JobDev* single_job, int single_k, const ee::Unit* units,
                       int n_units, int* queue, const ee::JobDev* const* jobtab, uint32_t flags,
                       int n_therm, int g0, int grid, int block, int lds_bytes, void* stream) {
   const void* fn = nullptr;
-  hipError_t e = (hipError_t)ee_k_sweep_kernel_ptr(dim, &fn);
+  hipError_t e = (hipError_t)ee_k_sweep_kernel_ptr(wide, &fn);
   if (e != hipSuccess) return (int)e;
-  (void)dim;
-  hipLaunchKernelGGL(sweep_kernel, dim3(grid), dim3(block), lds_bytes, (hipStream_t)stream, single_job,
-                     single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
+  if (wide)
+    hipLaunchKernelGGL(sweep_kernel_wide, dim3(grid), dim3(block), lds_bytes, (hipStream_t)stream, single_job,
+                       single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
+  else
+    hipLaunchKernelGGL(sweep_kernel, dim3(grid), dim3(block), lds_bytes, (hipStream_t)stream, single_job,
+                       single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
   return (int)hipGetLastError();
 }
 

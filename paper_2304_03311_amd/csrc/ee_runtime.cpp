@@ -203,6 +203,7 @@ struct Plan {
   ee_launch_cfg cfg{};
   int dim = 0;
   int block = 0, lds = 0, grid = 0, n_units = 0;
+  int wide = 0;  // which sweep kernel (pick_wide)
   void* dev_buf = nullptr;
   int* dev_queue = nullptr;
   const ee::JobDev** dev_jobtab = nullptr;
@@ -271,6 +272,20 @@ ee_status stream_sweeps(ee_job* j, int n_sweeps, bool protocol) {
   return EE_OK;
 }
 
+// Sweep kernel for an on-chip launch of `block` threads and `lds` bytes per
+// workgroup: the forced one, else the wide (4-wave) kernel when the narrow
+// one could not hold more than 4 waves per SIMD with this LDS use anyway.
+int pick_wide(uint32_t launch_flags, int block, int lds) {
+  if (launch_flags & EE_LAUNCH_WIDE) return 1;
+  if (launch_flags & EE_LAUNCH_NARROW) return 0;
+  const void* fn = nullptr;
+  if (ee_k_sweep_kernel_ptr(0, &fn) != 0) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess || per_cu < 1) return 0;
+  const int waves_per_simd = per_cu * ((block + 63) / 64) / 4;  // 4 SIMDs per CU
+  return waves_per_simd <= 4 ? 1 : 0;
+}
+
 ee_status launch_sweep_for_job(ee_job* j, uint32_t flags, int n_therm) {
   if (j->streaming) {
     if (flags & ee::kFlagInit) {
@@ -286,8 +301,8 @@ ee_status launch_sweep_for_job(ee_job* j, uint32_t flags, int n_therm) {
                              2 * device_info().cus);
   const int grid = (j->d.n_traj + k - 1) / k;
   const int lds = k * j->L.traj_words * 4;
-  const int rc = ee_k_launch_sweep(j->d.dim, j->dev_jobdev(), k, nullptr, 0, nullptr, nullptr, flags,
-                                   n_therm, (int)j->g, grid, block, lds, j->stream);
+  const int rc = ee_k_launch_sweep(pick_wide(j->cfg.flags, block, lds), j->dev_jobdev(), k, nullptr, 0, nullptr,
+                                   nullptr, flags, n_therm, (int)j->g, grid, block, lds, j->stream);
   if (rc != 0) return fail(EE_EHIP, "sweep kernel launch failed: %s", hipGetErrorString((hipError_t)rc));
   return EE_OK;
 }
@@ -300,7 +315,10 @@ ee_status check_cfg(const ee_launch_cfg* cfg) {
   if (cfg->lds_bytes < 0 || cfg->lds_bytes > ee_k_max_lds_bytes())
     return fail(EE_EINVAL, "lds_bytes must be in [0, %d]", ee_k_max_lds_bytes());
   if (cfg->grid_blocks < 0) return fail(EE_EINVAL, "grid_blocks must be >= 0");
-  if (cfg->flags & ~EE_LAUNCH_STREAMING) return fail(EE_EINVAL, "unknown launch flags 0x%x", cfg->flags);
+  if (cfg->flags & ~(EE_LAUNCH_STREAMING | EE_LAUNCH_WIDE | EE_LAUNCH_NARROW))
+    return fail(EE_EINVAL, "unknown launch flags 0x%x", cfg->flags);
+  if ((cfg->flags & EE_LAUNCH_WIDE) && (cfg->flags & EE_LAUNCH_NARROW))
+    return fail(EE_EINVAL, "EE_LAUNCH_WIDE and EE_LAUNCH_NARROW exclude each other");
   return EE_OK;
 }
 
@@ -333,8 +351,9 @@ ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launc
   P->lds = lds_need;
   P->n_units = (int)units.size();
   // persistent grid: as many workgroups as fit on the GPU at once
+  P->wide = pick_wide(cfg.flags, P->block, P->lds);
   const void* fn = nullptr;
-  int rc = ee_k_sweep_kernel_ptr(P->dim, &fn);
+  int rc = ee_k_sweep_kernel_ptr(P->wide, &fn);
   if (rc != 0) { delete P; return fail(EE_EHIP, "kernel attribute: %s", hipGetErrorString((hipError_t)rc)); }
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, P->block, P->lds);
@@ -419,7 +438,7 @@ ee_status run_plan(Plan* P, hipStream_t stream) {
     int rc = ee_k_launch_queue_reset(P->dev_queue, stream);
     if (rc) return fail(EE_EHIP, "queue reset launch: %s", hipGetErrorString((hipError_t)rc));
     HIP_TRY(hipEventRecord(P->ev_start, stream));
-    rc = ee_k_launch_sweep(P->dim, nullptr, 0, P->dev_units, P->n_units, P->dev_queue, P->dev_jobtab,
+    rc = ee_k_launch_sweep(P->wide, nullptr, 0, P->dev_units, P->n_units, P->dev_queue, P->dev_jobtab,
                            ee::kFlagInit | ee::kFlagProto, P->n_therm, 0, P->grid, P->block, P->lds, stream);
     if (rc) return fail(EE_EHIP, "persistent sweep launch: %s", hipGetErrorString((hipError_t)rc));
     HIP_TRY(hipEventRecord(P->ev_stop, stream));

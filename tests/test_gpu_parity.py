@@ -172,6 +172,54 @@ def test_launch_shapes_give_identical_bits(cfg):
         j.close()
 
 
+WIDE_SPECS = [
+    # lx/2 a multiple of 16: lanes of the wide kernel take four words (16 sites)
+    dict(dim=2, lt=16, lx=32, ly=1, n=2, beta=BC2, l=13, n_step=8, n_traj=6, seed=31),
+    dict(dim=2, lt=8, lx=64, ly=1, n=3, beta=BC2, l=37, n_step=6, n_traj=5, seed=32, reverse=True),
+    dict(dim=2, lt=4, lx=96, ly=1, n=2, beta=0.3, l=70, n_step=5, n_traj=3, seed=33, spin_format=1),
+    dict(dim=3, lt=8, lx=32, ly=4, n=2, beta=BC3, l=22, n_step=8, n_traj=4, seed=34, subsets=True),
+    dict(dim=2, lt=6, lx=32, ly=1, n=2, beta=BC2, l=31, n_step=4, n_traj=3, seed=35),
+]
+
+
+@pytest.mark.parametrize("cfg", [dict(flags=ee.EE_LAUNCH_WIDE, block_threads=256),
+                                 dict(flags=ee.EE_LAUNCH_WIDE, block_threads=128, lds_bytes=32768),
+                                 dict(flags=ee.EE_LAUNCH_WIDE, block_threads=1024, use_graph=0),
+                                 dict(flags=ee.EE_LAUNCH_NARROW, block_threads=512),
+                                 dict()])
+def test_wide_and_narrow_kernels_give_identical_bits(cfg):
+    specs = [ee.JobSpec(**kw) for kw in WIDE_SPECS]
+    say(f"[gpu] sweep kernel choice {cfg}")
+    jobs = [ee.Job(s) for s in specs]
+    ee.batch_run(jobs, 4, cfg=cfg)
+    for s, j in zip(specs, jobs):
+        I_or, sp_or = eo.run(oracle_job(s), 4, want_spins=True)
+        assert np.array_equal(j.work(), I_or), s
+        assert np.array_equal(j.spins(), sp_or), s
+        j.close()
+    for s in specs:
+        j = ee.Job(s)
+        j.set_launch(cfg)
+        j.thermalize(4)
+        j.run_protocol()
+        I_or, sp_or = eo.run(oracle_job(s), 4, want_spins=True)
+        assert np.array_equal(j.work(), I_or), s
+        assert np.array_equal(j.spins(), sp_or), s
+        j.close()
+
+
+def test_launch_flags_are_checked():
+    s = ee.JobSpec(dim=2, lt=8, lx=32, ly=1, n=2, beta=0.4, l=2, n_step=4, n_traj=2, seed=1)
+    job = ee.Job(s)
+    with pytest.raises(ee.EEError) as e:
+        job.set_launch(dict(flags=ee.EE_LAUNCH_WIDE | ee.EE_LAUNCH_NARROW))
+    assert e.value.status == ee.EE_EINVAL
+    with pytest.raises(ee.EEError) as e:
+        job.set_launch(dict(flags=8))
+    assert e.value.status == ee.EE_EINVAL
+    job.close()
+
+
 def test_state_machine_errors():
     s = ee.JobSpec(dim=2, lt=8, lx=8, ly=1, n=2, beta=0.4, l=2, n_step=4, n_traj=2, seed=1)
     job = ee.Job(s)
