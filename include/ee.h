@@ -124,8 +124,9 @@ typedef struct ee_job ee_job; /* opaque host-side handle */
 
 /* Device bytes a job needs (spins of every trajectory, works, threshold
  * tables, result).  No device work.  EE_EINVAL for a bad description,
- * EE_EUNSUPPORTED for a bit-packed job whose trajectory does not fit the
- * on-chip (LDS) tile (such lattices are streamed from HBM in INT8). */
+ * EE_EUNSUPPORTED for a bit-packed job that cannot run on chip: its
+ * trajectory exceeds one workgroup's LDS, or a row has more than 1024
+ * words (lx/2 > 4096 sites).  Such lattices are streamed from HBM in INT8. */
 ee_status ee_job_footprint(const ee_job_desc* desc, size_t* bytes);
 
 /* Validate desc, build the geometry and the uint32 threshold tables on the
@@ -183,7 +184,9 @@ ee_status ee_batch_run(ee_job* const* jobs, int32_t count, int32_t n_therm, void
 
 /* Launch shape of the sweep kernel (what the autotuner varies). */
 typedef struct {
-  int32_t block_threads;   /* threads per workgroup: 64..1024, multiple of 64; 0 = default */
+  int32_t block_threads;   /* threads per workgroup: 64..1024, multiple of 64; 0 = default;
+                              raised to ceil(lx/8) rounded up to 64 when smaller (one lane
+                              per word of a row)                                           */
   int32_t lds_bytes;       /* LDS budget per workgroup (bytes); 0 = default               */
   int32_t grid_blocks;     /* persistent workgroups; 0 = one wave of the whole GPU          */
   int32_t use_graph;       /* 1 = record/replay a HIP graph (default), 0 = direct launches  */

@@ -129,15 +129,69 @@ __device__ __forceinline__ JP load_jp(const JobDev* J) {
 }
 
 // Per-lane iteration state of one work unit (the same for every sweep): the
-// lane owns words w .. w+W-1 of rows row0, row0 + nrg, ...; wl / wr are the
-// words left and right of that group (periodic in x); (r0, t0, y0) is the
-// first row decoded and nrg = dr*R + dt*ly + dy the row stride.
+// lane owns words w .. w+W-1 of niter rows; wl / wr are the words left and
+// right of that group (periodic in x).  The first row is (r0, t0, y0) at
+// word offset rowbase0; each next row is dr replicas, dt time slices and dy
+// rows of y further on, step words further in storage; when t wraps, r
+// moves by rinc and the offset back by wrapadj.
 struct Lane {
   int w, wl, wr;
-  int row0, nrg;
+  int niter, rowbase0, step;
   int r0, t0, y0;
   int dr, dt, dy;
+  int rinc, wrapadj;
 };
+
+// Lane map of the rows of one colour plane (n replicas x R = lt*ly rows of G
+// words) over T lanes, GW = G/W lanes per row, S = T/GW row slots.
+//  * S >= n: slot s takes replica s / B, B = S/n, and rows k, k+B, ... of
+//    that replica in the order rho = (k + 2 ly) mod R, so that the rows
+//    next to the cut (t = 0, 1) come last: one iteration of the lane's loop
+//    meets them instead of one per replica.
+//  * S < n: slot s takes rows s, s+S, ... of the planes in storage order.
+// The rows of a colour are independent within a half-sweep, so the order
+// does not change any result.
+__device__ __forceinline__ Lane make_lane(const JP& P, int lt_, int T, int W) {
+  const int GW = P.G / W;
+  const int S = T / GW;
+  const int slot = lt_ / GW;
+  Lane ln;
+  ln.w = (lt_ % GW) * W;
+  ln.wl = (ln.w == 0) ? P.G - 1 : ln.w - 1;
+  ln.wr = (ln.w + W == P.G) ? 0 : ln.w + W;
+  if (S >= P.n) {
+    const int B = S / P.n;
+    const int k0 = slot % B;
+    ln.r0 = slot / B;
+    ln.niter = (ln.r0 < P.n && k0 < P.R) ? (P.R - k0 + B - 1) / B : 0;
+    int rho = k0 + 2 * P.ly;
+    if (rho >= P.R) rho -= P.R;
+    ln.t0 = rho / P.ly;
+    ln.y0 = rho - ln.t0 * P.ly;
+    ln.rowbase0 = (ln.r0 * P.R + rho) * P.G;
+    ln.step = B * P.G;
+    const int b = B % P.R;
+    ln.dr = 0;
+    ln.dt = b / P.ly;
+    ln.dy = b - ln.dt * P.ly;
+    ln.rinc = 0;
+    ln.wrapadj = P.R * P.G;
+  } else {
+    const int nrows = P.n * P.R;
+    ln.niter = (slot < S && slot < nrows) ? (nrows - slot + S - 1) / S : 0;
+    ln.r0 = slot / P.R;
+    ln.t0 = (slot - ln.r0 * P.R) / P.ly;
+    ln.y0 = slot - ln.r0 * P.R - ln.t0 * P.ly;
+    ln.rowbase0 = slot * P.G;
+    ln.step = S * P.G;
+    ln.dr = S / P.R;
+    ln.dt = (S - ln.dr * P.R) / P.ly;
+    ln.dy = S - ln.dr * P.R - ln.dt * P.ly;
+    ln.rinc = 1;
+    ln.wrapadj = 0;
+  }
+  return ln;
+}
 
 __device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) { return (a ^ b) + c; }
 
@@ -179,6 +233,34 @@ __device__ __forceinline__ uint32_t min_u16x2(uint32_t a, uint32_t b) {
                                                                 __builtin_bit_cast(u16x2, b)));
 }
 
+// The W consecutive words p[0..W-1] of a lane as one 4W-byte access.  Where
+// W > 1, p is 4W-byte aligned (w, the row pitch G and every plane and
+// trajectory offset are multiples of W), and the lanes of a wave then cover
+// consecutive LDS banks; W separate dword accesses at a lane stride of W
+// words would conflict W-fold.
+template <int W>
+__device__ __forceinline__ void ld_words(const uint32_t* p, uint32_t v[W]) {
+  if constexpr (W == 4) {
+    const uint4 x = *reinterpret_cast<const uint4*>(p);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else if constexpr (W == 2) {
+    const uint2 x = *reinterpret_cast<const uint2*>(p);
+    v[0] = x.x; v[1] = x.y;
+  } else {
+    v[0] = p[0];
+  }
+}
+template <int W>
+__device__ __forceinline__ void st_words(uint32_t* p, const uint32_t v[W]) {
+  if constexpr (W == 4) {
+    *reinterpret_cast<uint4*>(p) = make_uint4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (W == 2) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(v[0], v[1]);
+  } else {
+    p[0] = v[0];
+  }
+}
+
 // 16-bit half hi (0 low, 1 high) of a Philox output word.
 __device__ __forceinline__ uint32_t half16(uint32_t word, int hi) { return hi ? (word >> 16) : (word & 0xFFFFu); }
 
@@ -211,7 +293,6 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
   const int cw = P.n * P.R * G;  // words per colour plane
   uint32_t* __restrict__ Lc = L + c * cw;
   const uint32_t* __restrict__ Lo = L + (c ^ 1) * cw;
-  const int nrows = P.n * P.R;
   const int LyG = P.ly * G;
   const int ltLyG = P.lt * LyG;
   const int ywrap = (P.ly - 1) * G;
@@ -225,13 +306,11 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
   const uint32_t fmask = valid & 0x01010101u;  // bit 0 of every real site's byte
   const uint32_t rshift = (w == G - 1) ? (uint32_t)tailsh : 24u;
   int r = ln.r0, t = ln.t0, y = ln.y0;
-  int rowbase = ln.row0 * G;
-  const int step = ln.nrg * G;
-  for (int row = ln.row0; row < nrows; row += ln.nrg, rowbase += step) {
+  int rowbase = ln.rowbase0;
+  for (int it = 0; it < ln.niter; ++it) {
     const int p = (c + t + y) & 1;  // x parity of this row's sites
     uint32_t A[W], B[W], S[W], a[W];
-#pragma unroll
-    for (int q = 0; q < W; ++q) A[q] = Lo[rowbase + w + q];
+    ld_words<W>(Lo + rowbase + w, A);
     if (FULL) {
       // the sites' x-1 (p = 0) or x+1 (p = 1) neighbours straddle two words
       const uint32_t E = Lo[rowbase + (p ? ln.wr : ln.wl)];
@@ -252,27 +331,30 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
     const int om = rowbase + w - LyG + ((t == 0) ? ltLyG : 0);
     const int op = rowbase + w + LyG - ((t == P.lt - 1) ? ltLyG : 0);
     uint32_t Tm[W], Tp[W];
+    ld_words<W>(Lc + rowbase + w, S);
+    ld_words<W>(Lo + om, Tm);
+    ld_words<W>(Lo + op, Tp);
 #pragma unroll
-    for (int q = 0; q < W; ++q) {
-      S[q] = Lc[rowbase + w + q];
-      Tm[q] = Lo[om + q];
-      Tp[q] = Lo[op + q];
-      a[q] = xad(A[q], S[q], xad(B[q], S[q], xad(Tm[q], S[q], Tp[q] ^ S[q])));
-    }
+    for (int q = 0; q < W; ++q) a[q] = xad(A[q], S[q], xad(B[q], S[q], xad(Tm[q], S[q], Tp[q] ^ S[q])));
     if (DIM == 3) {
       const int oym = rowbase + ((y == 0) ? ywrap : -G) + w;
       const int oyp = rowbase + ((y == P.ly - 1) ? -ywrap : G) + w;
+      uint32_t Ym[W], Yp[W];
+      ld_words<W>(Lo + oym, Ym);
+      ld_words<W>(Lo + oyp, Yp);
 #pragma unroll
-      for (int q = 0; q < W; ++q) a[q] = xad(Lo[oym + q], S[q], xad(Lo[oyp + q], S[q], a[q]));
+      for (int q = 0; q < W; ++q) a[q] = xad(Ym[q], S[q], xad(Yp[q], S[q], a[q]));
     }
     if (t <= 1) {
       // Row next to the cut: for glued columns x < l the temporal partner
       // across the cut is in replica r+1 (t = 0) or r-1 (t = 1).
       const int og = glued_row(P, r, t, y) * G + w;
       const uint32_t t0mask = (t == 0) ? 0xFFFFFFFFu : 0u;
+      uint32_t Tgl[W];
+      ld_words<W>(Lo + og, Tgl);
 #pragma unroll
       for (int q = 0; q < W; ++q) {
-        const uint32_t Tg = Lo[og + q];
+        const uint32_t Tg = Tgl[q];
         const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
         // own-replica partner across the cut: Tp on t = 0, Tm on t = 1
         const uint32_t Tcut = (Tp[q] & t0mask) | (Tm[q] & ~t0mask);
@@ -291,7 +373,7 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
     // a tie.
     // Call k serves words 2k and 2k+1 of the lane (W >= 2) or, with W = 1,
     // the lane's word alone, whose fields start at output word ob.
-    const uint32_t c0 = (uint32_t)((row - r * P.R) * P.G8 + (w >> 1));
+    const uint32_t c0 = (uint32_t)((t * P.ly + y) * P.G8 + (w >> 1));
     const uint32_t c3 = ctr3 | ((uint32_t)r << 1);
     const int ob = (W == 1) ? 2 * (w & 1) : 0;
     uint32_t f[W];
@@ -378,18 +460,25 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
         }
       }
     }
+    uint32_t Snew[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) {
       // S ^ ((f >> 7) & fmask) in one three-input op (table 0x78 = a ^ (b & c))
-      Lc[rowbase + w + q] = __builtin_amdgcn_bitop3_b32(S[q], f[q] >> 7, fmask, 0x78);
+      Snew[q] = __builtin_amdgcn_bitop3_b32(S[q], f[q] >> 7, fmask, 0x78);
     }
+    st_words<W>(Lc + rowbase + w, Snew);
     // next row of this lane
+    rowbase += ln.step;
     if (DIM == 3) {
       y += ln.dy;
       if (y >= P.ly) { y -= P.ly; ++t; }
     }
     t += ln.dt;
-    if (t >= P.lt) { t -= P.lt; ++r; }
+    if (t >= P.lt) {
+      t -= P.lt;
+      r += ln.rinc;
+      rowbase -= ln.wrapadj;
+    }
     r += ln.dr;
   }
 }
@@ -468,20 +557,8 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
     if (flags & ee::kFlagInit) init_spins(P, L, j, lt_, T);
     else load_spins(P, L, j, lt_, T);
   }
-  const int GW = P.G / W;  // word groups per row
-  Lane ln;
-  ln.w = (lt_ % GW) * W;
-  ln.wl = (ln.w == 0) ? P.G - 1 : ln.w - 1;
-  ln.wr = (ln.w + W == P.G) ? 0 : ln.w + W;
-  ln.row0 = lt_ / GW;
-  ln.nrg = T / GW;
-  ln.r0 = ln.row0 / P.R;
-  ln.t0 = (ln.row0 - ln.r0 * P.R) / P.ly;
-  ln.y0 = ln.row0 - ln.r0 * P.R - ln.t0 * P.ly;
-  ln.dr = ln.nrg / P.R;
-  ln.dt = (ln.nrg - ln.dr * P.R) / P.ly;
-  ln.dy = ln.nrg - ln.dr * P.R - ln.dt * P.ly;
-  const bool on = active && ln.row0 < ln.nrg;
+  const Lane ln = make_lane(P, lt_, T, W);
+  const bool on = active && ln.niter > 0;
   __syncthreads();
 
   int dI = 0;
@@ -549,7 +626,7 @@ template <int WMAX>
 __device__ __forceinline__ void sweep_body(const JobDev* single_job, int single_k, const Unit* units, int n_units,
                                            int* queue, const JobDev* const* jobtab, uint32_t flags, int n_therm,
                                            int g0) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ int s_unit;
   __shared__ int s_dI[ee::kMaxSlots];
   __shared__ uint32_t s_thr[8];
@@ -612,21 +689,9 @@ __device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int la
   const int lt_ = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t j = blockIdx.y;
   uint32_t* L = P.spins + (size_t)j * P.traj_words;
-  const int GW = P.G / W;
-  Lane ln;
-  ln.w = (lt_ % GW) * W;
-  ln.wl = (ln.w == 0) ? P.G - 1 : ln.w - 1;
-  ln.wr = (ln.w + W == P.G) ? 0 : ln.w + W;
-  ln.row0 = lt_ / GW;
-  ln.nrg = lanes / GW;
-  ln.r0 = ln.row0 / P.R;
-  ln.t0 = (ln.row0 - ln.r0 * P.R) / P.ly;
-  ln.y0 = ln.row0 - ln.r0 * P.R - ln.t0 * P.ly;
-  ln.dr = ln.nrg / P.R;
-  ln.dt = (ln.nrg - ln.dr * P.R) / P.ly;
-  ln.dy = ln.nrg - ln.dr * P.R - ln.dt * P.ly;
   int dI = 0;
-  if (lt_ < lanes && ln.row0 < ln.nrg) half_sweep<DIM, FULL, true, W>(P, ln, L, s_thr, c, g, j, pos, dpos, work, dI);
+  const Lane ln = make_lane(P, lt_ < lanes ? lt_ : 0, lanes, W);
+  if (lt_ < lanes && ln.niter > 0) half_sweep<DIM, FULL, true, W>(P, ln, L, s_thr, c, g, j, pos, dpos, work, dI);
   if (dI != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.work[j]), (unsigned long long)(long long)dI);
 }
 

@@ -135,6 +135,17 @@ DeviceInfo device_info() {
 }
 
 constexpr int kDefaultBlock = 1024;
+constexpr int kMaxBlock = 1024;
+
+// The on-chip sweep needs one lane per word of a row in every workgroup:
+// threads >= G, rounded up to whole waves.
+int min_block(const Layout& L) { return (L.G + 63) / 64 * 64; }
+
+// A job runs on chip when one trajectory fits a workgroup's LDS and one row
+// fits a workgroup's lanes; otherwise it is streamed from HBM.
+bool fits_on_chip(const Layout& L) {
+  return L.traj_words * 4 <= ee_k_max_lds_bytes() && min_block(L) <= kMaxBlock;
+}
 constexpr int kDefaultLdsBudget = 80 * 1024;  // two workgroups per CU
 
 // Trajectories per workgroup that maximise the trajectories finished per
@@ -295,7 +306,7 @@ ee_status launch_sweep_for_job(ee_job* j, uint32_t flags, int n_therm) {
     if (flags & ee::kFlagProto) return stream_sweeps(j, j->d.n_step, true);
     return stream_sweeps(j, n_therm, false);
   }
-  const int block = j->cfg.block_threads > 0 ? j->cfg.block_threads : kDefaultBlock;
+  const int block = std::max(j->cfg.block_threads > 0 ? j->cfg.block_threads : kDefaultBlock, min_block(j->L));
   const int budget = j->cfg.lds_bytes > 0 ? j->cfg.lds_bytes : kDefaultLdsBudget;
   const int k = choose_slots(j->L, j->d.n_replicas, block, std::max(budget, j->L.traj_words * 4), j->d.n_traj,
                              2 * device_info().cus);
@@ -330,6 +341,7 @@ ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launc
   P->cfg = cfg;
   P->dim = jobs[0]->d.dim;
   P->block = cfg.block_threads > 0 ? cfg.block_threads : kDefaultBlock;
+  for (int i = 0; i < count; ++i) P->block = std::max(P->block, min_block(jobs[i]->L));
   int budget = cfg.lds_bytes > 0 ? cfg.lds_bytes : kDefaultLdsBudget;
   for (int i = 0; i < count; ++i) budget = std::max(budget, jobs[i]->L.traj_words * 4);
   // units: per job, blocks of k trajectories; longest first
@@ -461,10 +473,11 @@ ee_status ee_job_footprint(const ee_job_desc* desc, size_t* bytes) {
   ee_status s = validate(desc);
   if (s) return s;
   Layout L = layout_of(desc);
-  if (L.traj_words * 4 > ee_k_max_lds_bytes() && desc->spin_format != EE_SPINS_INT8)
+  if (!fits_on_chip(L) && desc->spin_format != EE_SPINS_INT8)
     return fail(EE_EUNSUPPORTED,
-                "a trajectory of %d bytes exceeds the on-chip tile (%d bytes); such lattices are streamed "
-                "from HBM and need EE_SPINS_INT8 storage", L.traj_words * 4, ee_k_max_lds_bytes());
+                "a trajectory of %d bytes with rows of %d words exceeds the on-chip tile (%d bytes, %d words "
+                "per row); such lattices are streamed from HBM and need EE_SPINS_INT8 storage",
+                L.traj_words * 4, L.G, ee_k_max_lds_bytes(), kMaxBlock);
   *bytes = L.total;
   return EE_OK;
 }
@@ -492,7 +505,7 @@ ee_status ee_job_create(const ee_job_desc* desc, void* dev_arena, size_t arena_b
   j->est_enqueued = false;
   j->est_stream = j->stream;
   j->cfg = ee_launch_cfg{0, 0, 0, 1, 0};
-  j->streaming = j->L.traj_words * 4 > ee_k_max_lds_bytes();
+  j->streaming = !fits_on_chip(j->L);
   const int dim = desc->dim, N = desc->n_step;
   const bool subsets = (desc->flags & EE_FLAG_SUBSETS) != 0;
   const int S = subsets ? N / desc->ly : N;  // weights in units of beta/S
@@ -553,7 +566,7 @@ ee_status ee_job_set_launch(ee_job* job, const ee_launch_cfg* cfg) {
   if (force_stream && job->spins_exist && !job->streaming)
     return fail(EE_ESTATE, "switch to the streaming path before the first ee_thermalize");
   job->cfg = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1, 0};
-  job->streaming = force_stream || job->L.traj_words * 4 > ee_k_max_lds_bytes();
+  job->streaming = force_stream || !fits_on_chip(job->L);
   return EE_OK;
 }
 

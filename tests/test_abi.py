@@ -85,6 +85,17 @@ def test_too_large_for_lds_streams_in_int8_only():
     assert ei.value.status == ee.EE_EUNSUPPORTED
 
 
+def test_rows_wider_than_a_workgroup_stream_in_int8_only():
+    # lx = 8200: 4100 sites of a colour per row = 1025 words, more than the
+    # 1024 lanes of a workgroup; the trajectory itself (32 KiB) would fit LDS
+    assert ee.ee_job_footprint(_spec(lt=2, lx=8200).desc()) > 0
+    with pytest.raises(ee.EEError) as e:
+        ee.ee_job_footprint(_spec(lt=2, lx=8200, spin_format=1).desc())
+    assert e.value.status == ee.EE_EUNSUPPORTED
+    # 1024 words per row still run on chip, also bit-packed
+    assert ee.ee_job_footprint(_spec(lt=2, lx=8192, spin_format=1).desc()) > 0
+
+
 def test_null_arguments():
     L = ee.lib()
     assert L.ee_job_footprint(None, None) == ee.EE_EINVAL

@@ -5,6 +5,7 @@ within the tolerance derived from the estimator's arithmetic (see DF_TOL).
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 import sys
 
@@ -206,6 +207,44 @@ def test_wide_and_narrow_kernels_give_identical_bits(cfg):
         assert np.array_equal(j.work(), I_or), s
         assert np.array_equal(j.spins(), sp_or), s
         j.close()
+
+
+@pytest.mark.parametrize("cfg", [dict(block_threads=64), dict(block_threads=64, flags=ee.EE_LAUNCH_WIDE), dict()])
+def test_rows_wider_than_the_requested_block(cfg):
+    # lx = 2048: 256 words per row; a 64-thread block is raised to 256 so
+    # that every word of a row has a lane
+    s = ee.JobSpec(dim=2, lt=4, lx=2048, ly=1, n=2, beta=BC2, l=1001, n_step=3, n_traj=3, seed=41)
+    say(f"[gpu] wide rows {cfg}")
+    I_or, sp_or = eo.run(oracle_job(s), 2, want_spins=True)
+    j = ee.Job(s)
+    j.set_launch(cfg)
+    j.thermalize(2)
+    j.run_protocol()
+    assert np.array_equal(j.work(), I_or)
+    assert np.array_equal(j.spins(), sp_or)
+    j.close()
+    jobs = [ee.Job(s), ee.Job(dataclasses.replace(s, lx=64, l=5, seed=42))]
+    ee.batch_run(jobs, 2, cfg=cfg)
+    assert np.array_equal(jobs[0].work(), I_or)
+    assert np.array_equal(jobs[0].spins(), sp_or)
+    I2, sp2 = eo.run(oracle_job(jobs[1].spec), 2, want_spins=True)
+    assert np.array_equal(jobs[1].work(), I2)
+    assert np.array_equal(jobs[1].spins(), sp2)
+    for j in jobs:
+        j.close()
+
+
+def test_rows_wider_than_a_workgroup_stream():
+    # 1025 words per row: streamed from HBM although the trajectory is small
+    s = ee.JobSpec(dim=2, lt=2, lx=8200, ly=1, n=2, beta=BC2, l=4099, n_step=3, n_traj=2, seed=43)
+    say("[gpu] rows of 1025 words")
+    j = ee.Job(s)
+    j.thermalize(2)
+    j.run_protocol()
+    I_or, sp_or = eo.run(oracle_job(s), 2, want_spins=True)
+    assert np.array_equal(j.work(), I_or)
+    assert np.array_equal(j.spins(), sp_or)
+    j.close()
 
 
 def test_launch_flags_are_checked():
