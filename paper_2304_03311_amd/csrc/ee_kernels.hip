@@ -202,7 +202,8 @@ __device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) { re
 // FULL: lx/2 is a multiple of 4 (no pad bytes, x-neighbours by byte
 // alignment of two words).  UJ: the trajectory index is uniform per wave.
 // W: consecutive words per lane (2 or 4 need FULL and a word count that W
-// divides).
+// divides; 3 needs FULL and rows of exactly three words, so that w = 0 and
+// words 0, 1 share a Philox call while word 2 takes the next one).
 // Ramp position (0..S) of row y when the protocol stands at position pos
 // (0..N): every row follows pos, or (subset protocol) row y moves during
 // steps [y S, (y+1) S).
@@ -234,10 +235,11 @@ __device__ __forceinline__ uint32_t min_u16x2(uint32_t a, uint32_t b) {
 }
 
 // The W consecutive words p[0..W-1] of a lane as one 4W-byte access.  Where
-// W > 1, p is 4W-byte aligned (w, the row pitch G and every plane and
+// W is 2 or 4, p is 4W-byte aligned (w, the row pitch G and every plane and
 // trajectory offset are multiples of W), and the lanes of a wave then cover
 // consecutive LDS banks; W separate dword accesses at a lane stride of W
-// words would conflict W-fold.
+// words would conflict W-fold.  W = 3 (rows of three words, one lane per
+// row) reads dwords: an odd lane stride does not conflict.
 template <int W>
 __device__ __forceinline__ void ld_words(const uint32_t* p, uint32_t v[W]) {
   if constexpr (W == 4) {
@@ -247,7 +249,8 @@ __device__ __forceinline__ void ld_words(const uint32_t* p, uint32_t v[W]) {
     const uint2 x = *reinterpret_cast<const uint2*>(p);
     v[0] = x.x; v[1] = x.y;
   } else {
-    v[0] = p[0];
+#pragma unroll
+    for (int q = 0; q < W; ++q) v[q] = p[q];
   }
 }
 template <int W>
@@ -257,7 +260,8 @@ __device__ __forceinline__ void st_words(uint32_t* p, const uint32_t v[W]) {
   } else if constexpr (W == 2) {
     *reinterpret_cast<uint2*>(p) = make_uint2(v[0], v[1]);
   } else {
-    p[0] = v[0];
+#pragma unroll
+    for (int q = 0; q < W; ++q) p[q] = v[q];
   }
 }
 
@@ -286,7 +290,7 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
                                            const uint32_t* __restrict__ thr, const int c,
                                            const uint32_t g, uint32_t j, const int pos, const int dpos,
                                            const bool work, int& dI) {
-  static_assert(W == 1 || ((W == 2 || W == 4) && FULL), "several words per lane need whole rows");
+  static_assert(W == 1 || ((W == 2 || W == 3 || W == 4) && FULL), "several words per lane need whole rows");
   constexpr int NC = (W + 1) / 2;  // Philox calls per row: 8 sites each
   if (UJ) j = __builtin_amdgcn_readfirstlane(j);
   const int G = P.G;
@@ -589,9 +593,10 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
 
 // Words per lane for a job and slot size of T lanes: the widest W <= wmax
 // (4 or 2) that divides the row's words and still gives every row a lane
-// group.
+// group; with wmax = 4, rows of exactly three words take W = 3.
 __device__ __forceinline__ int words_per_lane(const JP& P, int T, int wmax) {
   if (wmax >= 4 && (P.H & 15) == 0 && T / (P.G / 4) >= 1) return 4;
+  if (wmax >= 4 && P.H == 12) return 3;
   return ((P.H & 7) == 0 && T / (P.G / 2) >= 1) ? 2 : 1;
 }
 
@@ -607,6 +612,11 @@ __device__ __forceinline__ void run_unit_dispatch(const JP& P, uint32_t* lds, in
     if (wpl == 4) {
       if (uj) run_unit<DIM, true, true, 4>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
       else run_unit<DIM, true, false, 4>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      return;
+    }
+    if (wpl == 3) {
+      if (uj) run_unit<DIM, true, true, 3>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      else run_unit<DIM, true, false, 3>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
       return;
     }
   }
