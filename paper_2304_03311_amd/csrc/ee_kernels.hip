@@ -129,14 +129,15 @@ __device__ __forceinline__ JP load_jp(const JobDev* J) {
 }
 
 // Per-lane iteration state of one work unit (the same for every sweep): the
-// lane owns words w .. w+W-1 of niter rows; wl / wr are the words left and
-// right of that group (periodic in x).  The first row is (r0, t0, y0) at
-// word offset rowbase0; each next row is dr replicas, dt time slices and dy
-// rows of y further on, step words further in storage; when t wraps, r
-// moves by rinc and the offset back by wrapadj.
+// lane owns words w .. w+W-1 of the rows numbered kstart, kstart + kstep,
+// ... below kend; wl / wr are the words left and right of that group
+// (periodic in x).  The first row is (r0, t0, y0) at word offset rowbase0;
+// each next row is dr replicas, dt time slices and dy rows of y further
+// on, step words further in storage; when t wraps, r moves by rinc and the
+// offset back by wrapadj.
 struct Lane {
   int w, wl, wr;
-  int niter, rowbase0, step;
+  int kstart, kstep, kend, rowbase0, step;
   int r0, t0, y0;
   int dr, dt, dy;
   int rinc, wrapadj;
@@ -150,43 +151,51 @@ struct Lane {
 //    meets them instead of one per replica.
 //  * S < n: slot s takes rows s, s+S, ... of the planes in storage order.
 // The rows of a colour are independent within a half-sweep, so the order
-// does not change any result.
+// does not change any result.  Divisions by R and ly use the job's magic
+// multipliers (the streaming kernel builds this map at every launch).
 __device__ __forceinline__ Lane make_lane(const JP& P, int lt_, int T, int W) {
   const int GW = P.G / W;
   const int S = T / GW;
   const int slot = lt_ / GW;
+  const auto div_ly = [&](int v) { return (int)fdiv((uint32_t)v, P.mLy, P.sLy); };
+  const auto div_R = [&](int v) { return (int)fdiv((uint32_t)v, P.mR, P.sR); };
   Lane ln;
-  ln.w = (lt_ % GW) * W;
+  ln.w = (lt_ - slot * GW) * W;
   ln.wl = (ln.w == 0) ? P.G - 1 : ln.w - 1;
   ln.wr = (ln.w + W == P.G) ? 0 : ln.w + W;
   if (S >= P.n) {
     const int B = S / P.n;
-    const int k0 = slot % B;
     ln.r0 = slot / B;
-    ln.niter = (ln.r0 < P.n && k0 < P.R) ? (P.R - k0 + B - 1) / B : 0;
+    const int k0 = slot - ln.r0 * B;
+    ln.kstart = k0;
+    ln.kstep = B;
+    ln.kend = (ln.r0 < P.n) ? P.R : 0;
     int rho = k0 + 2 * P.ly;
     if (rho >= P.R) rho -= P.R;
-    ln.t0 = rho / P.ly;
+    ln.t0 = div_ly(rho);
     ln.y0 = rho - ln.t0 * P.ly;
     ln.rowbase0 = (ln.r0 * P.R + rho) * P.G;
     ln.step = B * P.G;
-    const int b = B % P.R;
+    const int b = B - div_R(B) * P.R;  // B mod R
     ln.dr = 0;
-    ln.dt = b / P.ly;
+    ln.dt = div_ly(b);
     ln.dy = b - ln.dt * P.ly;
     ln.rinc = 0;
     ln.wrapadj = P.R * P.G;
   } else {
-    const int nrows = P.n * P.R;
-    ln.niter = (slot < S && slot < nrows) ? (nrows - slot + S - 1) / S : 0;
-    ln.r0 = slot / P.R;
-    ln.t0 = (slot - ln.r0 * P.R) / P.ly;
-    ln.y0 = slot - ln.r0 * P.R - ln.t0 * P.ly;
+    ln.kstart = slot;
+    ln.kstep = S;
+    ln.kend = (slot < S) ? P.n * P.R : 0;
+    ln.r0 = div_R(slot);
+    const int rho = slot - ln.r0 * P.R;
+    ln.t0 = div_ly(rho);
+    ln.y0 = rho - ln.t0 * P.ly;
     ln.rowbase0 = slot * P.G;
     ln.step = S * P.G;
-    ln.dr = S / P.R;
-    ln.dt = (S - ln.dr * P.R) / P.ly;
-    ln.dy = S - ln.dr * P.R - ln.dt * P.ly;
+    ln.dr = div_R(S);
+    const int b = S - ln.dr * P.R;
+    ln.dt = div_ly(b);
+    ln.dy = b - ln.dt * P.ly;
     ln.rinc = 1;
     ln.wrapadj = 0;
   }
@@ -311,7 +320,7 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
   const uint32_t rshift = (w == G - 1) ? (uint32_t)tailsh : 24u;
   int r = ln.r0, t = ln.t0, y = ln.y0;
   int rowbase = ln.rowbase0;
-  for (int it = 0; it < ln.niter; ++it) {
+  for (int kk = ln.kstart; kk < ln.kend; kk += ln.kstep) {
     const int p = (c + t + y) & 1;  // x parity of this row's sites
     uint32_t A[W], B[W], S[W], a[W];
     ld_words<W>(Lo + rowbase + w, A);
@@ -562,7 +571,7 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
     else load_spins(P, L, j, lt_, T);
   }
   const Lane ln = make_lane(P, lt_, T, W);
-  const bool on = active && ln.niter > 0;
+  const bool on = active && ln.kstart < ln.kend;
   __syncthreads();
 
   int dI = 0;
@@ -701,7 +710,7 @@ __device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int la
   uint32_t* L = P.spins + (size_t)j * P.traj_words;
   int dI = 0;
   const Lane ln = make_lane(P, lt_ < lanes ? lt_ : 0, lanes, W);
-  if (lt_ < lanes && ln.niter > 0) half_sweep<DIM, FULL, true, W>(P, ln, L, s_thr, c, g, j, pos, dpos, work, dI);
+  if (lt_ < lanes && ln.kstart < ln.kend) half_sweep<DIM, FULL, true, W>(P, ln, L, s_thr, c, g, j, pos, dpos, work, dI);
   if (dI != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.work[j]), (unsigned long long)(long long)dI);
 }
 
