@@ -184,7 +184,9 @@ ee_status ee_batch_run(ee_job* const* jobs, int32_t count, int32_t n_therm, void
 
 /* Launch shape of the sweep kernel (what the autotuner varies). */
 typedef struct {
-  int32_t block_threads;   /* threads per workgroup: 64..1024, multiple of 64; 0 = default;
+  int32_t block_threads;   /* threads per workgroup: 64..1024, multiple of 64; 0 = about
+                              one thread per four words of a trajectory's colour plane
+                              (n*lt*ly*ceil(lx/8)/4, rounded up to 64, at most 1024);
                               raised to ceil(lx/8) rounded up to 64 when smaller (one lane
                               per word of a row)                                           */
   int32_t lds_bytes;       /* LDS budget per workgroup (bytes); 0 = default               */

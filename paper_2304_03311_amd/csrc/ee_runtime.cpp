@@ -141,6 +141,29 @@ constexpr int kMaxBlock = 1024;
 // threads >= G, rounded up to whole waves.
 int min_block(const Layout& L) { return (L.G + 63) / 64 * 64; }
 
+// Default block for a job when the caller gives none: about one lane per
+// four row-words of a trajectory (n * R * G words in a colour plane), so
+// that small lattices do not leave most lanes of a 1024-thread block idle,
+// within [min_block, kDefaultBlock].
+int default_block(const Layout& L, int n_rep) {
+  const long words = (long)n_rep * L.R * L.G;
+  const long want = (words + 3) / 4;
+  int b = (int)std::min<long>(kDefaultBlock, (want + 63) / 64 * 64);
+  return std::max(b, std::max(64, min_block(L)));
+}
+
+// Default block of a job launched alone (per-job path): when its
+// trajectories cannot fill the GPU's threads with one lane per row-word,
+// take that many lanes per trajectory (every lane one row: lowest
+// latency); otherwise share the GPU's threads out over the trajectories.
+int job_block(const Layout& L, const ee_job_desc& d) {
+  const long words = (long)d.n_replicas * L.R * L.G;
+  const long capacity = (long)device_info().cus * 2048;
+  const long per_traj = std::max(64L, std::min(words, capacity / std::max(1, d.n_traj)));
+  const int b = (int)std::min<long>(kDefaultBlock, (per_traj + 63) / 64 * 64);
+  return std::max(b, min_block(L));
+}
+
 // A job runs on chip when one trajectory fits a workgroup's LDS and one row
 // fits a workgroup's lanes; otherwise it is streamed from HBM.
 bool fits_on_chip(const Layout& L) {
@@ -306,7 +329,7 @@ ee_status launch_sweep_for_job(ee_job* j, uint32_t flags, int n_therm) {
     if (flags & ee::kFlagProto) return stream_sweeps(j, j->d.n_step, true);
     return stream_sweeps(j, n_therm, false);
   }
-  const int block = std::max(j->cfg.block_threads > 0 ? j->cfg.block_threads : kDefaultBlock, min_block(j->L));
+  const int block = std::max(j->cfg.block_threads > 0 ? j->cfg.block_threads : job_block(j->L, j->d), min_block(j->L));
   const int budget = j->cfg.lds_bytes > 0 ? j->cfg.lds_bytes : kDefaultLdsBudget;
   const int k = choose_slots(j->L, j->d.n_replicas, block, std::max(budget, j->L.traj_words * 4), j->d.n_traj,
                              2 * device_info().cus);
@@ -340,7 +363,12 @@ ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launc
   P->n_therm = n_therm;
   P->cfg = cfg;
   P->dim = jobs[0]->d.dim;
-  P->block = cfg.block_threads > 0 ? cfg.block_threads : kDefaultBlock;
+  if (cfg.block_threads > 0) {
+    P->block = cfg.block_threads;
+  } else {
+    P->block = 64;
+    for (int i = 0; i < count; ++i) P->block = std::max(P->block, default_block(jobs[i]->L, jobs[i]->d.n_replicas));
+  }
   for (int i = 0; i < count; ++i) P->block = std::max(P->block, min_block(jobs[i]->L));
   int budget = cfg.lds_bytes > 0 ? cfg.lds_bytes : kDefaultLdsBudget;
   for (int i = 0; i < count; ++i) budget = std::max(budget, jobs[i]->L.traj_words * 4);
