@@ -704,11 +704,30 @@ sweep_kernel_wide(const JobDev* single_job, int single_k, const Unit* units, int
 // path.  The neighbour rows are read through the vector caches, and the
 // integer work goes to HBM with 64-bit atomics.
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched to the XCDs (kXcd of them, each with its own L2)
+// in turn by workgroup id.  The grid is one-dimensional, bx blocks per
+// trajectory; the physical id is mapped to a logical (trajectory, block)
+// such that each XCD gets one contiguous run of logical blocks, i.e. whole
+// trajectories and neighbouring rows, which then meet in one L2.  The map
+// is a bijection of [0, total), so results do not depend on it.
+constexpr int kXcd = 8;
+__device__ __forceinline__ void xcd_block(int bx, int total, int& j, int& b) {
+  const int id = blockIdx.x;
+  const int q = total / kXcd, rem = total - q * kXcd;
+  const int x = id % kXcd, k = id / kXcd;
+  const int logical = (x < rem) ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+  j = logical / bx;
+  b = logical - j * bx;
+}
+
 template <int DIM, bool FULL, int W>
 __device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int lanes, int c, uint32_t g, int pos,
                                             int dpos, bool work) {
-  const int lt_ = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t j = blockIdx.y;
+  const int bx = (lanes + 255) / 256;
+  int jj, b;
+  xcd_block(bx, (int)gridDim.x, jj, b);
+  const int lt_ = b * blockDim.x + threadIdx.x;
+  const uint32_t j = (uint32_t)jj;
   uint32_t* L = P.spins + (size_t)j * P.traj_words;
   int dI = 0;
   const Lane ln = make_lane(P, lt_ < lanes ? lt_ : 0, lanes, W, false);
@@ -904,7 +923,8 @@ int ee_k_launch_sweep(int wide, const ee::JobDev* single_job, int single_k, cons
 int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos, int dpos,
                              int work, void* stream) {
   const int bx = (lanes + 255) / 256;
-  hipLaunchKernelGGL(stream_sweep_kernel, dim3(bx, n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c, g,
+  // one-dimensional grid: bx blocks per trajectory, remapped per XCD in the kernel
+  hipLaunchKernelGGL(stream_sweep_kernel, dim3(bx * n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c, g,
                      pos, dpos, work);
   return (int)hipGetLastError();
 }
