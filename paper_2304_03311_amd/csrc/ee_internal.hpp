@@ -86,7 +86,8 @@ int ee_k_sweep_kernel_ptr(int wide, const void** fn);
 int ee_k_queue_reset_ptr(const void** fn);
 int ee_k_estimate_ptr(const void** fn);
 int ee_k_max_lds_bytes();
-int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos, int dpos,
+// wide: 1 = the 4-wave streaming kernel (up to four words per lane).
+int ee_k_launch_stream_sweep(int wide, const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos, int dpos,
                              int work, void* stream);
 int ee_k_launch_stream_init(const ee::JobDev* job, int n_traj, int lanes, void* stream);
 int ee_k_launch_zero_work(const ee::JobDev* job, int n_traj, void* stream);

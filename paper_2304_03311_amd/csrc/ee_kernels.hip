@@ -735,8 +735,11 @@ __device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int la
   if (dI != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.work[j]), (unsigned long long)(long long)dI);
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
-stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int pos, int dpos, int work) {
+// Body of the streaming launches: the widest lane width the entry point
+// compiles (WMAX) that the job's rows allow.
+template <int WMAX>
+__device__ __forceinline__ void stream_body(const JobDev* J, int lanes, int c, uint32_t g, int pos, int dpos,
+                                            int work) {
   __shared__ uint32_t s_thr[8];
   const JP P = load_jp(J);
   const int dim = uni(J->dim);
@@ -744,17 +747,42 @@ stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int pos, int 
     s_thr[threadIdx.x] = (threadIdx.x == 0) ? P.thr0 : (threadIdx.x == 1) ? P.thr1
                        : (threadIdx.x == 2 && dim == 3) ? P.thr2 : 0xFFFFFFFFu;
   __syncthreads();
-  const bool two = words_per_lane(P, lanes, 2) == 2;
+  const int wpl = words_per_lane(P, lanes, WMAX);
   const bool full = (P.H & 3) == 0;
+  if constexpr (WMAX >= 4) {
+    if (wpl == 4) {
+      if (dim == 3) stream_half<3, true, 4>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+      else stream_half<2, true, 4>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+      return;
+    }
+    if (wpl == 3) {
+      if (dim == 3) stream_half<3, true, 3>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+      else stream_half<2, true, 3>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+      return;
+    }
+  }
   if (dim == 3) {
-    if (two) stream_half<3, true, 2>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+    if (wpl == 2) stream_half<3, true, 2>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
     else if (full) stream_half<3, true, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
     else stream_half<3, false, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
   } else {
-    if (two) stream_half<2, true, 2>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+    if (wpl == 2) stream_half<2, true, 2>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
     else if (full) stream_half<2, true, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
     else stream_half<2, false, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
   }
+}
+
+// 8 waves per SIMD, one or two words per lane.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int pos, int dpos, int work) {
+  stream_body<2>(J, lanes, c, g, pos, dpos, work);
+}
+
+// 4 waves per SIMD (128 VGPRs), up to four words per lane: rows whose
+// half-length is a multiple of 16 sites.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+stream_sweep_kernel_wide(const JobDev* J, int lanes, int c, uint32_t g, int pos, int dpos, int work) {
+  stream_body<4>(J, lanes, c, g, pos, dpos, work);
 }
 
 // Initial spins of every trajectory, written straight to HBM.
@@ -920,12 +948,16 @@ int ee_k_launch_sweep(int wide, const ee::JobDev* single_job, int single_k, cons
   return (int)hipGetLastError();
 }
 
-int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos, int dpos,
-                             int work, void* stream) {
+int ee_k_launch_stream_sweep(int wide, const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos,
+                             int dpos, int work, void* stream) {
   const int bx = (lanes + 255) / 256;
   // one-dimensional grid: bx blocks per trajectory, remapped per XCD in the kernel
-  hipLaunchKernelGGL(stream_sweep_kernel, dim3(bx * n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c, g,
-                     pos, dpos, work);
+  if (wide)
+    hipLaunchKernelGGL(stream_sweep_kernel_wide, dim3(bx * n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c,
+                       g, pos, dpos, work);
+  else
+    hipLaunchKernelGGL(stream_sweep_kernel, dim3(bx * n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c, g,
+                       pos, dpos, work);
   return (int)hipGetLastError();
 }
 

@@ -280,9 +280,13 @@ bool same_cfg(const ee_launch_cfg& a, const ee_launch_cfg& b) {
 }
 
 // Lanes per trajectory of the streaming path: every lane walks about 8 rows.
+// Streaming launches with rows of a multiple of 16 sites per colour use the
+// 4-wave kernel with four words per lane.
+bool stream_wide(const ee_job* j) { return (j->L.H & 15) == 0; }
+
 int stream_lanes(const ee_job* j) {
   const int nrows = j->d.n_replicas * j->L.R;
-  const int W = ((j->L.H & 7) == 0) ? 2 : 1;
+  const int W = stream_wide(j) ? 4 : ((j->L.H & 7) == 0) ? 2 : 1;
   const int GW = j->L.G / W;
   const int nrg = std::max(1, (nrows + 7) / 8);
   return nrg * GW;
@@ -290,6 +294,7 @@ int stream_lanes(const ee_job* j) {
 
 ee_status stream_sweeps(ee_job* j, int n_sweeps, bool protocol) {
   const int lanes = stream_lanes(j);
+  const int wide = stream_wide(j) ? 1 : 0;
   const int nt = j->d.n_traj;
   int rc = 0;
   if (protocol) rc = ee_k_launch_zero_work(j->dev_jobdev(), nt, j->stream);
@@ -299,8 +304,8 @@ ee_status stream_sweeps(ee_job* j, int n_sweeps, bool protocol) {
   const int dpos = protocol ? (rev ? -1 : 1) : 0;
   for (int s = 0; s < n_sweeps && rc == 0; ++s, ++g) {
     const int pos = protocol ? (rev ? N - 1 - s : s + 1) : (rev ? N : 0);
-    rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 0, g, pos, dpos, protocol ? 1 : 0, j->stream);
-    if (rc == 0) rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 1, g, pos, dpos, 0, j->stream);
+    rc = ee_k_launch_stream_sweep(wide, j->dev_jobdev(), nt, lanes, 0, g, pos, dpos, protocol ? 1 : 0, j->stream);
+    if (rc == 0) rc = ee_k_launch_stream_sweep(wide, j->dev_jobdev(), nt, lanes, 1, g, pos, dpos, 0, j->stream);
   }
   if (rc) return fail(EE_EHIP, "streaming sweep launch failed: %s", hipGetErrorString((hipError_t)rc));
   return EE_OK;

@@ -359,6 +359,25 @@ def test_streaming_path_matches_oracle(name, kw, n_therm):
     job.close()
 
 
+WIDE_STREAM = [kw for kw in WIDE_SPECS if kw.get("spin_format", 0) == 0]
+
+
+@pytest.mark.parametrize("kw", WIDE_STREAM, ids=[f"lx{kw['lx']}_d{kw['dim']}" for kw in WIDE_STREAM])
+def test_streaming_with_wide_rows_matches_oracle(kw):
+    """Rows of a multiple of 16 sites per colour stream through the 4-wave
+    kernel with four words per lane (rows of three words take W = 3)."""
+    s = ee.JobSpec(**kw)
+    say(f"[gpu] streaming wide rows {kw}")
+    job = ee.Job(s)
+    job.set_launch({"flags": ee.EE_LAUNCH_STREAMING})
+    job.thermalize(3)
+    job.run_protocol()
+    I_or, sp_or = eo.run(oracle_job(s), 3, want_spins=True)
+    assert np.array_equal(job.work(), I_or)
+    assert np.array_equal(job.spins(), sp_or)
+    job.close()
+
+
 @pytest.mark.parametrize("kw", [
     dict(dim=3, lt=48, lx=48, ly=48, n=2, beta=BC3, l=20, n_step=10, n_traj=4, seed=31),
     dict(dim=2, lt=1024, lx=128, ly=1, n=2, beta=BC2, l=64, n_step=6, n_traj=2, seed=32, reverse=True),
