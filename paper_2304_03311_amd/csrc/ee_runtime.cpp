@@ -279,16 +279,17 @@ bool same_cfg(const ee_launch_cfg& a, const ee_launch_cfg& b) {
          a.grid_blocks == b.grid_blocks && a.use_graph == b.use_graph && a.flags == b.flags;
 }
 
-// Lanes per trajectory of the streaming path: every lane walks about 8 rows.
 // Streaming launches with rows of a multiple of 16 sites per colour use the
 // 4-wave kernel with four words per lane.
 bool stream_wide(const ee_job* j) { return (j->L.H & 15) == 0; }
 
+// Lanes per trajectory of the streaming path: every lane walks about 4 rows
+// (measured on 96^3: 4% faster than 8 rows, and faster than 2).
 int stream_lanes(const ee_job* j) {
   const int nrows = j->d.n_replicas * j->L.R;
   const int W = stream_wide(j) ? 4 : ((j->L.H & 7) == 0) ? 2 : 1;
   const int GW = j->L.G / W;
-  const int nrg = std::max(1, (nrows + 7) / 8);
+  const int nrg = std::max(1, (nrows + 3) / 4);
   return nrg * GW;
 }
 
