@@ -175,6 +175,8 @@ def main() -> int:
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--no-tune", action="store_true", help="library default launch shape instead of the tuner's")
     ap.add_argument("--no-configs", action="store_true", help="skip the c1/c3/c4 job sets")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="run only the HBM-streaming measurement (3D 96^3) and print its JSON (profiled runs)")
     ap.add_argument("--launch", default=None,
                     help='launch shape as JSON (ee_launch_cfg fields), e.g. \'{"block_threads": 256, '
                          '"lds_bytes": 54272, "flags": 2}\'; replaces the tuner (used for profiled runs)')
@@ -192,6 +194,9 @@ def main() -> int:
     from paper_2304_03311_amd import analysis, autotune, ee, serve, workloads
 
     torch.cuda.set_device(0)
+    if args.stream_only:
+        print(json.dumps({"streaming_path": streaming_run()}), flush=True)
+        return 0
     specs = workloads.config2_jobs()
     stream = torch.cuda.current_stream()
     n_therm = workloads.N_THERM
