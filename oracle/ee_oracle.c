@@ -18,6 +18,10 @@
  *     linearly, beta^(k,k) = beta (1 - m/N), beta^(k,k+1) = beta m/N
  *     (Sec. 3, linear protocol), so lambda = 0 is A(l) and lambda = 1 is
  *     A(l+1);
+ *   - the whole-region protocol reviewed in Sec. 3 (flag bit 2): every cut
+ *     link of A = {x < l} is ramped at once, intra beta (1 - m/N), inter
+ *     beta m/N, from n decoupled replicas (lambda = 0) to A(l) glued
+ *     (lambda = 1), so Delta F = (n-1) S_n(l) directly;
  *   - work on phi_k, then an update at lambda_{k+1} (App. A, eq. for the
  *     work in one Monte Carlo step and the discretised average);
  *   - exp(-W) averaged over trajectories (App. A, Jarzynski's equality),
@@ -35,6 +39,8 @@
  *   Cut       the +t bond of (r,0,y,x): x <  l -> ((r+1)%n, 1, y, x)
  *                                       x == l -> ramped (intra + inter)
  *                                       x >  l -> (r, 1, y, x)
+ *             whole-region protocol:    x <  l -> ramped (intra + inter)
+ *                                       x >= l -> (r, 1, y, x)
  *   Weights   integer, in units of beta/N: bulk N, ramped intra N-m,
  *             ramped inter m.  H/T = -(beta/N) sum_b w_b s_a s_b.  (With
  *             subsets, below, N is replaced by S everywhere.)
@@ -168,7 +174,9 @@ static int geom_build(geom* G, int dim, int lt, int lx, int ly, int n, double be
   if (dim != 2 && dim != 3) return EO_EINVAL;
   if (dim == 2 && ly != 1) return EO_EINVAL;
   if (lt < 2 || lx < 2 || ly < 1 || (lt & 1) || (lx & 1) || (dim == 3 && ((ly & 1) || ly < 2))) return EO_EINVAL;
-  if (n < 2 || !(beta >= 0.0) || l < 0 || l >= lx || N < 1 || n_traj < 0) return EO_EINVAL;
+  const int whole = (flags >> 2) & 1;
+  if (n < 2 || !(beta >= 0.0) || N < 1 || n_traj < 0) return EO_EINVAL;
+  if (whole ? (l < 1 || l > lx || (flags & 2)) : (l < 0 || l >= lx)) return EO_EINVAL;
   G->dim = dim; G->lt = lt; G->lx = lx; G->ly = ly; G->n = n; G->beta = beta;
   G->l = l; G->N = N; G->n_traj = n_traj; G->seed = seed; G->reverse = flags & 1;
   G->subsets = (flags >> 1) & 1;
@@ -176,7 +184,8 @@ static int geom_build(geom* G, int dim, int lt, int lx, int ly, int n, double be
   G->S = G->subsets ? N / ly : N;
   G->V = (int64_t)lt * ly * lx;
   G->nsites = (int64_t)n * G->V;
-  int64_t maxb = G->nsites * dim + (int64_t)n * ly; /* ramped column adds one bond per (r,y) */
+  /* a ramped column adds one bond per (r,y) */
+  int64_t maxb = G->nsites * dim + (int64_t)n * ly * (whole ? l : 1);
   G->ba = (int64_t*)malloc(sizeof(int64_t) * maxb);
   G->bb = (int64_t*)malloc(sizeof(int64_t) * maxb);
   G->bk = (int8_t*)malloc(maxb);
@@ -189,7 +198,12 @@ static int geom_build(geom* G, int dim, int lt, int lx, int ly, int n, double be
           int64_t s = site_index(G, r, t, y, x);
           add_bond(G, s, site_index(G, r, t, y, (x + 1) % lx), BOND_BULK, y);          /* +x */
           if (dim == 3) add_bond(G, s, site_index(G, r, t, (y + 1) % ly, x), BOND_BULK, y); /* +y */
-          if (t == 0 && x < l) {                                                      /* glued */
+          if (whole && t == 0 && x < l) {                                             /* ramped */
+            add_bond(G, s, site_index(G, r, 1, y, x), BOND_INTRA, y);
+            add_bond(G, s, site_index(G, (r + 1) % n, 1, y, x), BOND_INTER, y);
+          } else if (whole) {                                                         /* +t */
+            add_bond(G, s, site_index(G, r, (t + 1) % lt, y, x), BOND_BULK, y);
+          } else if (t == 0 && x < l) {                                               /* glued */
             add_bond(G, s, site_index(G, (r + 1) % n, 1, y, x), BOND_BULK, y);
           } else if (t == 0 && x == l) {                                              /* ramped */
             add_bond(G, s, site_index(G, r, 1, y, x), BOND_INTRA, y);

@@ -22,6 +22,8 @@ the paper's definitions, and independent of both the C oracle
 Conventions (same reading of the paper as the C oracle): the +t bond of
 (r,0,y,x) goes to ((r+1)%n,1,y,x) for x<l, is ramped for x==l (intra weight
 N-m, inter weight m, in units of beta/N) and stays in replica r otherwise.
+The whole-region protocol (Sec. 3) ramps the bonds of every x < l instead and
+glues none.
 """
 from __future__ import annotations
 
@@ -50,12 +52,29 @@ class Lattice:
         return ((r * self.lt + t) * self.ly + y) * self.lx + x
 
 
-def bonds(lat: Lattice, glued_upto: int | None = None, ramp: bool = True):
+def bonds(lat: Lattice, glued_upto: int | None = None, ramp: bool = True, whole: bool = False):
     """Bond list [(a, b, kind, y)] of the replica lattice (y: the row of the bond).
 
     ``glued_upto`` overrides l for the glued columns x < glued_upto; with
     ``ramp=False`` no column is ramped (a pure geometry A(glued_upto)).
+    ``whole=True``: the columns x < l are all ramped and none is glued.
     """
+    if whole:
+        out = []
+        for r in range(lat.n):
+            for t in range(lat.lt):
+                for y in range(lat.ly):
+                    for x in range(lat.lx):
+                        s = lat.index(r, t, y, x)
+                        out.append((s, lat.index(r, t, y, (x + 1) % lat.lx), BULK, y))
+                        if lat.dim == 3:
+                            out.append((s, lat.index(r, t, (y + 1) % lat.ly, x), BULK, y))
+                        if t == 0 and x < lat.l:
+                            out.append((s, lat.index(r, 1, y, x), INTRA, y))
+                            out.append((s, lat.index((r + 1) % lat.n, 1, y, x), INTER, y))
+                        else:
+                            out.append((s, lat.index(r, (t + 1) % lat.lt, y, x), BULK, y))
+        return out
     l = lat.l if glued_upto is None else glued_upto
     out = []
     for r in range(lat.n):
@@ -214,7 +233,7 @@ def _site_coords(lat: Lattice):
 
 
 def exact_protocol(lat: Lattice, beta: float, N: int, start: str = "equilibrium",
-                   n_therm: int = 0, reverse: bool = False, subsets: bool = False):
+                   n_therm: int = 0, reverse: bool = False, subsets: bool = False, whole: bool = False):
     """Exact distribution of the integer work I over trajectories.
 
     start='equilibrium': phi_0 ~ pi at the starting ramp position.
@@ -230,12 +249,15 @@ def exact_protocol(lat: Lattice, beta: float, N: int, start: str = "equilibrium"
     move one after the other, row y during steps [y S, (y+1) S), S = N/Ly,
     with weights in units of beta/S (W = -(beta/S) I).
 
+    whole=True is the whole-region protocol of Sec. 3: the cut links of every
+    x < l move together, from n decoupled replicas to A(l).
+
     Returns (values, probs): the support of I and its probabilities.
     """
     ns = lat.nsites
     if ns > 20:
         raise ValueError("exact propagation limited to 20 spins")
-    b = bonds(lat)
+    b = bonds(lat, whole=whole)
     ba = np.array([x[0] for x in b])
     bb = np.array([x[1] for x in b])
     bk = np.array([x[2] for x in b])
@@ -276,7 +298,8 @@ def exact_protocol(lat: Lattice, beta: float, N: int, start: str = "equilibrium"
         return P
 
     m0 = m_of(-1)
-    Dmax = 2 * lat.n * (1 if subsets else lat.ly)  # bound on |D_k|: the rows that move in one step
+    # bound on |D_k|: two per ramped (replica, row, column) that moves in one step
+    Dmax = 2 * lat.n * (1 if subsets else lat.ly) * (lat.l if whole else 1)
     nI = 2 * Dmax * N + 1
     off = Dmax * N
     P = np.zeros((nI, nstates))

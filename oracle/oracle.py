@@ -72,6 +72,7 @@ class Job:
     seed: int
     reverse: bool = False
     subsets: bool = False  # protocol 2 of App. B: the Ly rows ramped one after the other
+    whole: bool = False  # whole-region protocol (Sec. 3): all cut links of x < l ramped at once
 
     @property
     def nsites(self) -> int:
@@ -79,7 +80,7 @@ class Job:
 
     @property
     def flags(self) -> int:
-        return (1 if self.reverse else 0) | (2 if self.subsets else 0)
+        return (1 if self.reverse else 0) | (2 if self.subsets else 0) | (4 if self.whole else 0)
 
     @property
     def S(self) -> int:

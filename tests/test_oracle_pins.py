@@ -482,3 +482,110 @@ def test_protocol2_work_is_energy_difference_and_needs_divisible_N():
             assert abs(dE) <= 2 * job.n
     with pytest.raises(ValueError):
         eo.run(eo.Job(3, 4, 4, 4, 2, BC3, 2, 6, 2, 9, False, subsets=True), 1)
+
+
+# --------------------------------------------------------------------------
+# Whole-region protocol (Sec. 3): every cut link of A = {x < l} ramped at
+# once, from n decoupled replicas to A(l), so Delta F = (n-1) S_n(l)
+# --------------------------------------------------------------------------
+
+def test_whole_region_exact_propagation_gives_renyi_entropy():
+    """The exact work law of the whole-region protocol reproduces
+    log Z_n(0) - log Z_n(l) (brute force; transfer matrix) for every N, and
+    its reverse the inverse."""
+    cases = [  # lattice, beta, protocol lengths N, also reversed
+        ((2, 2, 2, 1, 2, 1), BC2, (1, 2, 3), True),
+        ((2, 2, 2, 1, 2, 2), 0.4, (1, 2, 3), True),   # l = lx: every column
+        ((2, 2, 2, 1, 3, 2), 0.5, (1, 2), True),      # three replicas
+        ((2, 4, 2, 1, 2, 1), 0.6, (1, 2), False),
+        ((3, 2, 2, 2, 2, 2), BC3, (1,), False),
+    ]
+    for (dim, lt, lx, ly, n, l), beta, Ns, rev in cases:
+        lat = ex.Lattice(dim, lt, lx, ly, n, l)
+        lz0 = ex.log_z_bruteforce(ex.Lattice(dim, lt, lx, ly, n, 0), beta, ramp=False)
+        lzl = ex.log_z_bruteforce(lat, beta, glued_upto=l, ramp=False)
+        assert lzl == pytest.approx(ex.log_z_transfer(lat, beta, glued_upto=l, ramp=False), abs=1e-12)
+        for N in Ns:
+            v, p = ex.exact_protocol(lat, beta, N, whole=True)
+            assert -math.log(ex.jarzynski_average(v, p, beta, N)) == pytest.approx(lz0 - lzl, abs=2e-13)
+            if rev:
+                v, p = ex.exact_protocol(lat, beta, N, whole=True, reverse=True)
+                assert -math.log(ex.jarzynski_average(v, p, beta, N)) == pytest.approx(lzl - lz0, abs=2e-13)
+
+
+def test_whole_region_of_one_column_is_protocol1_from_no_cut():
+    """A(0) -> A(1) is both the whole-region protocol with l = 1 and the
+    c-function protocol with l = 0: the same geometry, bond for bond."""
+    for (dim, lt, lx, ly, n) in [(2, 8, 6, 1, 2), (3, 4, 6, 2, 3)]:
+        a = eo.Job(dim, lt, lx, ly, n, 0.44, 1, 12, 5, 7, whole=True)
+        b = eo.Job(dim, lt, lx, ly, n, 0.44, 0, 12, 5, 7)
+        Ia, sa = eo.run(a, 5, want_spins=True)
+        Ib, sb = eo.run(b, 5, want_spins=True)
+        assert np.array_equal(Ia, Ib) and np.array_equal(sa, sb)
+
+
+def test_whole_region_energy_endpoints_are_geometries():
+    """At m = 0 the replicas are decoupled, at m = N the columns x < l are
+    glued: the oracle's integer energy equals the pure-geometry energy."""
+    rng = np.random.default_rng(5)
+    for (dim, lt, lx, ly, n, l) in [(2, 4, 6, 1, 2, 3), (2, 4, 6, 1, 3, 6), (3, 4, 4, 2, 2, 2)]:
+        lat = ex.Lattice(dim, lt, lx, ly, n, l)
+        job = eo.Job(dim, lt, lx, ly, n, 0.3, l, 5, 1, 1, whole=True)
+        for _ in range(4):
+            s = rng.choice(np.array([-1, 1], dtype=np.int8), size=lat.nsites)
+            for m, glued in ((0, 0), (5, l)):
+                b = ex.bonds(lat, glued_upto=glued, ramp=False)
+                e = -sum(int(s[a]) * int(s[c]) for a, c, *_ in b) * 5
+                assert eo.energy_units(job, m, s) == e
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+def test_oracle_whole_region_matches_exact_propagation(reverse):
+    lat = ex.Lattice(2, 2, 2, 1, 3, 2)
+    N, n_therm = 3, 4
+    v, p = ex.exact_protocol(lat, 0.5, N, start="hot", n_therm=n_therm, reverse=reverse, whole=True)
+    job = eo.Job(2, 2, 2, 1, 3, 0.5, 2, N, 20000, 19, reverse, whole=True)
+    I, _ = eo.run(job, n_therm)
+    assert _chi2_pvalue(I, v, p) > 1e-4
+
+
+def test_whole_region_rejects_bad_l_and_subsets():
+    for l in (0, 7):
+        with pytest.raises(ValueError):
+            eo.run(eo.Job(2, 4, 6, 1, 2, 0.4, l, 3, 1, 1, whole=True), 1)
+    with pytest.raises(ValueError):
+        eo.run(eo.Job(3, 4, 4, 2, 2, 0.4, 1, 4, 1, 1, whole=True, subsets=True), 1)
+    eo.run(eo.Job(2, 4, 6, 1, 2, 0.4, 6, 3, 1, 1, whole=True), 1)  # l = lx: every column
+
+
+WHOLE_MUTATIONS = {
+    "whole: intra link not ramped": (
+        "if (whole && t == 0 && x < l) {                                             /* ramped */\n"
+        "            add_bond(G, s, site_index(G, r, 1, y, x), BOND_INTRA, y);",
+        "if (whole && t == 0 && x < l) {                                             /* ramped */\n"
+        "            add_bond(G, s, site_index(G, r, 1, y, x), BOND_BULK, y);"),
+    "whole: one column too few": ("if (whole && t == 0 && x < l) {", "if (whole && t == 0 && x < l - 1) {"),
+}
+# Not listed: gluing to replica r-1 instead of r+1.  With no column glued
+# before the ramp, the relabelling r -> -r maps one geometry onto the other
+# at every step, so the work law cannot see it; like the colour order, it is
+# a convention checked only by bit-exact parity of the GPU path.
+
+
+def test_planted_whole_region_mistakes_are_caught(tmp_path):
+    """Each plausible mistake in the whole-region geometry makes the exact
+    work law fail (three replicas so that the inter direction matters)."""
+    lat = ex.Lattice(2, 2, 2, 1, 3, 1)
+    v, p = ex.exact_protocol(lat, 0.6, 3, start="hot", n_therm=2, whole=True)
+    job = eo.Job(2, 2, 2, 1, 3, 0.6, 1, 3, 20000, 23, whole=True)
+    for name, (old, new) in WHOLE_MUTATIONS.items():
+        L = _build_mutant(tmp_path, name, old, new)
+        I = np.zeros(job.n_traj, dtype=np.int64)
+        rc = L.eo_run(job.dim, job.lt, job.lx, job.ly, job.n, job.beta, job.l, job.n_step, job.n_traj, job.seed,
+                      job.flags, 2, 0, job.n_traj, job.n_step, I.ctypes.data, None)
+        assert rc == 0
+        caught = (not np.all(np.isin(I, v))) or _chi2_pvalue(I, v, p) < 1e-6
+        assert caught, f"planted mistake '{name}' was not detected"
+    # the unmutated oracle passes the same check
+    I, _ = eo.run(job, 2)
+    assert _chi2_pvalue(I, v, p) > 1e-4
