@@ -80,13 +80,21 @@ typedef enum {
                               are then in units of beta/S and
                               W_j = -(beta/S) I_j.  Identical to the default
                               protocol in 2D.                               */
+#define EE_FLAG_WHOLE 4u   /* the whole-region protocol reviewed in Sec. 3:
+                              start from n decoupled replicas and ramp every
+                              cut link of A = {x < l} at once (intra
+                              beta (1 - m/N), inter beta m/N) to A(l)
+                              glued, so Delta F = (n-1) S_n(l) directly.
+                              Needs 1 <= l <= lx; not with EE_FLAG_SUBSETS.
+                              With EE_FLAG_REVERSE it starts from A(l).    */
 
 /*
  * Problem statement of one job, in the paper's terms (Sec. 3; Sec. 4 and 5
  * conventions: lattice extents, replica number n, beta, region size l,
  * protocol length N, trajectory count n_t).
  * Constraints: dim in {2,3}; lt, lx even >= 2; ly == 1 for dim 2, even >= 2
- * for dim 3; n_replicas >= 2; beta finite >= 0; 0 <= l < lx; n_step >= 1;
+ * for dim 3; n_replicas >= 2; beta finite >= 0; 0 <= l < lx (1 <= l <= lx
+ * with EE_FLAG_WHOLE); n_step >= 1;
  * 1 <= n_traj <= 65535.  Violations return EE_EINVAL.
  */
 typedef struct {

@@ -40,6 +40,7 @@ struct alignas(256) JobDev {
   int32_t packed_words; // bit-packed words per trajectory = 2*n*R*ceil(H/32)
   int32_t S;            // weight unit beta/S: N, or N/ly for the subset protocol
   int32_t subsets;      // EE_FLAG_SUBSETS: rows of the ramped column moved one at a time
+  int32_t whole;        // EE_FLAG_WHOLE: every cut link of x < l ramped, none glued
   uint32_t key0, key1;  // Philox key
   uint32_t thr_bulk[4]; // U for a = 0..dim-1 anti-aligned neighbours (bulk/glued sites)
   uint32_t reverse;     // EE_FLAG_REVERSE

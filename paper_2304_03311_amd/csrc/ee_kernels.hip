@@ -84,7 +84,7 @@ __device__ __forceinline__ void philox10_x02(uint32_t c0, uint32_t c1, uint32_t 
 
 // Per-job constants, held in scalar registers.
 struct JP {
-  int dim, n, lt, ly, l, N, S, subsets, H, G, G8, R, traj_words, packed_row_words;
+  int dim, n, lt, ly, l, N, S, subsets, whole, H, G, G8, R, traj_words, packed_row_words;
   uint32_t key0, key1, thr0, thr1, thr2, reverse, spin_format;
   uint32_t pt_hi0, pt_hi1, pt_lo0, pt_lo1;  // byte tables of (thr[a] >> 16) ^ 0x8000, a = 0..7
   uint32_t mR, sR, mLy, sLy;
@@ -97,7 +97,7 @@ __device__ __forceinline__ JP load_jp(const JobDev* J) {
   JP P;
   P.dim = uni(J->dim);
   P.n = uni(J->n); P.lt = uni(J->lt); P.ly = uni(J->ly); P.l = uni(J->l); P.N = uni(J->N);
-  P.S = uni(J->S); P.subsets = uni(J->subsets);
+  P.S = uni(J->S); P.subsets = uni(J->subsets); P.whole = uni(J->whole);
   P.H = uni(J->H); P.G = uni(J->G); P.R = uni(J->R); P.traj_words = uni(J->traj_words);
   P.G8 = (P.H + 7) >> 3;
   P.packed_row_words = (P.H + 31) >> 5;
@@ -360,7 +360,7 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
 #pragma unroll
       for (int q = 0; q < W; ++q) a[q] = xad(Ym[q], S[q], xad(Yp[q], S[q], a[q]));
     }
-    if (t <= 1) {
+    if (t <= 1 && !P.whole) {
       // Row next to the cut: for glued columns x < l the temporal partner
       // across the cut is in replica r+1 (t = 0) or r-1 (t = 1).
       const int og = glued_row(P, r, t, y) * G + w;
@@ -437,41 +437,90 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
         }
       }
     }
-    if (t <= 1 && p == ramp_p && (unsigned)(ramp_w - w) < (unsigned)W) {
-      // ramped site x = l of a row next to the cut (one lane per row): its
-      // threshold replaces the bulk decision taken above for its byte.
-      // K = s (S a_fix + (S-m) s_intra + m s_inter) in units of beta/S.
-      const int og = glued_row(P, r, t, y) * G + w;
-      const int oc = rowbase + ((t == 0) ? LyG : -LyG) + w;  // own-replica partner across the cut
-      const int m = row_m(P, y, pos);
-#pragma unroll
-      for (int q = 0; q < W; ++q) {
-        if (w + q != ramp_w) continue;
-        const uint32_t Tg = Lo[og + q];
-        const uint32_t Tcut = Lo[oc + q];
-        const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
-        const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
-        const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
-        const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
-        const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
-        const uint32_t Ur = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
-        const int ri = ramp_sh >> 3;
-        const int o = ((ob + 2 * q) & 3) + (ri >> 1);
-        uint32_t u1[4];
-        philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
-        const uint32_t vr = half16(pick4(u1, o), ri & 1);
-        uint32_t acc = vr < (Ur >> 16);
-        if (vr == (Ur >> 16)) {
-          uint32_t u2[4];
-          philox10(c0 + (q >> 1), g, j, c3 + (1u << 28), P.key0, P.key1, u2);
-          acc = half16(pick4(u2, o), ri & 1) <= (Ur & 0xFFFFu);
+    if (t <= 1) {
+      // rows next to the cut: the ramped sites (one column, or with the
+      // whole-region protocol every column x < l)
+      if (!P.whole && p == ramp_p && (unsigned)(ramp_w - w) < (unsigned)W) {
+        // ramped site x = l of a row next to the cut (one lane per row): its
+        // threshold replaces the bulk decision taken above for its byte.
+        // K = s (S a_fix + (S-m) s_intra + m s_inter) in units of beta/S.
+        const int og = glued_row(P, r, t, y) * G + w;
+        const int oc = rowbase + ((t == 0) ? LyG : -LyG) + w;  // own-replica partner across the cut
+        const int m = row_m(P, y, pos);
+  #pragma unroll
+        for (int q = 0; q < W; ++q) {
+          if (w + q != ramp_w) continue;
+          const uint32_t Tg = Lo[og + q];
+          const uint32_t Tcut = Lo[oc + q];
+          const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
+          const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
+          const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
+          const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
+          const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
+          const uint32_t Ur = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
+          const int ri = ramp_sh >> 3;
+          const int o = ((ob + 2 * q) & 3) + (ri >> 1);
+          uint32_t u1[4];
+          philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
+          const uint32_t vr = half16(pick4(u1, o), ri & 1);
+          uint32_t acc = vr < (Ur >> 16);
+          if (vr == (Ur >> 16)) {
+            uint32_t u2[4];
+            philox10(c0 + (q >> 1), g, j, c3 + (1u << 28), P.key0, P.key1, u2);
+            acc = half16(pick4(u2, o), ri & 1) <= (Ur & 0xFFFFu);
+          }
+          f[q] = (f[q] & ~(0xFFu << ramp_sh)) | (acc << (ramp_sh + 7));
+          if (work) {
+            // the ramped site of colour 0 sees phi_k: its bonds' weights moved
+            // by (m - m_prev), so the D_k term is (m - m_prev) 2 (b - c)
+            const int dm = m - row_m(P, y, pos - dpos);
+            dI += dm * 2 * ((int)bb - (int)cc);
+          }
         }
-        f[q] = (f[q] & ~(0xFFu << ramp_sh)) | (acc << (ramp_sh + 7));
-        if (work) {
-          // the ramped site of colour 0 sees phi_k: its bonds' weights moved
-          // by (m - m_prev), so the D_k term is (m - m_prev) 2 (b - c)
-          const int dm = m - row_m(P, y, pos - dpos);
-          dI += dm * 2 * ((int)bb - (int)cc);
+      }
+      if (P.whole && 8 * w + p < P.l) {
+        // whole-region protocol: every site x < l of a row next to the cut is
+        // ramped and none is glued.  Per site K = s (S a_fix + (S-m) s_intra +
+        // m s_inter) from the ramp table, replacing the bulk decision.
+        const int og = glued_row(P, r, t, y) * G + w;
+        const int oc = rowbase + ((t == 0) ? LyG : -LyG) + w;  // own-replica partner across the cut
+        const int m = row_m(P, y, pos);
+        const uint32_t* __restrict__ Um = P.ramp + m * (8 * DIM);
+        uint32_t Tgl[W], Tcl[W];
+        ld_words<W>(Lo + og, Tgl);
+        ld_words<W>(Lo + oc, Tcl);
+  #pragma unroll
+        for (int q = 0; q < W; ++q) {
+          const uint32_t rm = glued_mask(P.l - p - 8 * (w + q));  // bytes with x < l
+          if (rm == 0) continue;
+          const uint32_t bw = Tcl[q] ^ S[q];  // intra partner anti-aligned (bit 0 of each byte)
+          const uint32_t cw = Tgl[q] ^ S[q];  // inter partner anti-aligned
+          const uint32_t fw = a[q] - bw;      // the 2 dim - 1 fixed neighbours
+          uint32_t u1[4];
+          philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (!((rm >> (8 * i)) & 1u)) continue;
+            const uint32_t fa = (fw >> (8 * i)) & 0xFFu;
+            const uint32_t bb = (bw >> (8 * i)) & 1u;
+            const uint32_t cc = (cw >> (8 * i)) & 1u;
+            const uint32_t Ur = Um[fa * 4 + bb * 2 + cc];
+            const int o = ((ob + 2 * q) & 3) + (i >> 1);
+            const uint32_t vr = half16(pick4(u1, o), i & 1);
+            uint32_t acc = vr < (Ur >> 16);
+            if (vr == (Ur >> 16)) {
+              uint32_t u2[4];
+              philox10(c0 + (q >> 1), g, j, c3 + (1u << 28), P.key0, P.key1, u2);
+              acc = half16(pick4(u2, o), i & 1) <= (Ur & 0xFFFFu);
+            }
+            f[q] = (f[q] & ~(0xFFu << (8 * i))) | (acc << (8 * i + 7));
+          }
+          if (work) {
+            // colour-0 ramped sites see phi_k; each adds (m - m_prev) 2 (b - c)
+            const int dm = m - row_m(P, y, pos - dpos);
+            const uint32_t sel = rm & 0x01010101u;
+            dI += dm * 2 * (__popc(bw & sel) - __popc(cw & sel));
+          }
         }
       }
     }

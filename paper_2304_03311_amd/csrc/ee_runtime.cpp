@@ -77,13 +77,20 @@ ee_status validate(const ee_job_desc* d) {
     return fail(EE_EINVAL, "n_replicas must be in [2, 2^20] (got %d)", d->n_replicas);
   if (!(d->beta >= 0.0) || !std::isfinite(d->beta))
     return fail(EE_EINVAL, "beta must be finite and >= 0");
-  if (d->l < 0 || d->l >= d->lx) return fail(EE_EINVAL, "l must satisfy 0 <= l < lx (got %d)", d->l);
+  if (d->flags & EE_FLAG_WHOLE) {
+    if (d->l < 1 || d->l > d->lx)
+      return fail(EE_EINVAL, "the whole-region protocol needs 1 <= l <= lx (got %d)", d->l);
+    if (d->flags & EE_FLAG_SUBSETS) return fail(EE_EINVAL, "EE_FLAG_WHOLE and EE_FLAG_SUBSETS exclude each other");
+  } else if (d->l < 0 || d->l >= d->lx) {
+    return fail(EE_EINVAL, "l must satisfy 0 <= l < lx (got %d)", d->l);
+  }
   if (d->n_step < 1) return fail(EE_EINVAL, "n_step must be >= 1 (got %d)", d->n_step);
   if (d->n_traj < 1 || d->n_traj > 65535)
     return fail(EE_EINVAL, "n_traj must be in [1, 65535] (got %d)", d->n_traj);
   if (d->spin_format != EE_SPINS_INT8 && d->spin_format != EE_SPINS_BITPACKED)
     return fail(EE_EINVAL, "unknown spin_format %d", d->spin_format);
-  if (d->flags & ~(EE_FLAG_REVERSE | EE_FLAG_SUBSETS)) return fail(EE_EINVAL, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(EE_FLAG_REVERSE | EE_FLAG_SUBSETS | EE_FLAG_WHOLE))
+    return fail(EE_EINVAL, "unknown flags 0x%x", d->flags);
   if ((d->flags & EE_FLAG_SUBSETS) && d->n_step % d->ly)
     return fail(EE_EINVAL, "the subset protocol needs n_step divisible by ly (%d %% %d)", d->n_step, d->ly);
   // |I| <= 2 n ly N must fit the int32 accumulators
@@ -554,6 +561,7 @@ ee_status ee_job_create(const ee_job_desc* desc, void* dev_arena, size_t arena_b
   D.key1 = (uint32_t)(desc->seed >> 32);
   D.S = S;
   D.subsets = subsets ? 1 : 0;
+  D.whole = (desc->flags & EE_FLAG_WHOLE) ? 1 : 0;
   for (int a = 0; a < dim; ++a) D.thr_bulk[a] = threshold(desc->beta, (int64_t)S * (2 * dim - 2 * a), S);
   D.reverse = (desc->flags & EE_FLAG_REVERSE) ? 1u : 0u;
   D.spin_format = (uint32_t)desc->spin_format;

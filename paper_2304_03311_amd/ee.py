@@ -19,6 +19,7 @@ EE_OK, EE_EINVAL, EE_ENOMEM, EE_EHIP, EE_ESTATE, EE_EUNSUPPORTED = 0, -1, -2, -3
 EE_SPINS_INT8, EE_SPINS_BITPACKED = 0, 1
 EE_FLAG_REVERSE = 1
 EE_FLAG_SUBSETS = 2
+EE_FLAG_WHOLE = 4
 EE_LAUNCH_STREAMING = 1
 EE_LAUNCH_WIDE = 2
 EE_LAUNCH_NARROW = 4
@@ -203,9 +204,11 @@ class JobSpec:
     spin_format: int = EE_SPINS_INT8
     reverse: bool = False
     subsets: bool = False  # protocol 2 of App. B
+    whole: bool = False  # whole-region protocol of Sec. 3: Delta F = (n-1) S_n(l)
 
     def desc(self) -> ee_job_desc:
-        flags = (EE_FLAG_REVERSE if self.reverse else 0) | (EE_FLAG_SUBSETS if self.subsets else 0)
+        flags = ((EE_FLAG_REVERSE if self.reverse else 0) | (EE_FLAG_SUBSETS if self.subsets else 0)
+                 | (EE_FLAG_WHOLE if self.whole else 0))
         return make_desc(self.dim, self.lt, self.lx, self.ly, self.n, self.beta, self.l, self.n_step,
                          self.n_traj, self.seed, self.spin_format, flags)
 

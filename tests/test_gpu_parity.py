@@ -43,7 +43,8 @@ def df_tol(est: eo.Estimate, beta: float, N: int, n_t: int) -> float:
 
 
 def oracle_job(s: ee.JobSpec) -> eo.Job:
-    return eo.Job(s.dim, s.lt, s.lx, s.ly, s.n, s.beta, s.l, s.n_step, s.n_traj, s.seed, s.reverse, s.subsets)
+    return eo.Job(s.dim, s.lt, s.lx, s.ly, s.n, s.beta, s.l, s.n_step, s.n_traj, s.seed, s.reverse, s.subsets,
+                  s.whole)
 
 
 def check_estimate(res: ee.ee_result, I: np.ndarray, s: ee.JobSpec):
@@ -88,6 +89,14 @@ CASES = [
                                     subsets=True, spin_format=1), 3),
     ("2d_protocol2_is_protocol1", dict(dim=2, lt=8, lx=16, ly=1, n=2, beta=BC2, l=4, n_step=9, n_traj=4, seed=19,
                                        subsets=True), 3),
+    # whole-region protocol (Sec. 3): every cut link of x < l ramped at once
+    ("2d_whole_l3", dict(dim=2, lt=8, lx=12, ly=1, n=2, beta=BC2, l=3, n_step=10, n_traj=5, seed=51, whole=True), 4),
+    ("2d_whole_every_column_n3_reverse", dict(dim=2, lt=6, lx=8, ly=1, n=3, beta=0.5, l=8, n_step=6, n_traj=4,
+                                              seed=52, whole=True, reverse=True), 3),
+    ("2d_whole_ragged_lx70", dict(dim=2, lt=4, lx=70, ly=1, n=2, beta=0.42, l=41, n_step=4, n_traj=3, seed=54,
+                                  whole=True), 3),
+    ("3d_whole_bitpacked", dict(dim=3, lt=4, lx=10, ly=4, n=2, beta=BC3, l=7, n_step=5, n_traj=3, seed=53,
+                                whole=True, spin_format=1), 3),
 ]
 
 
@@ -184,6 +193,7 @@ WIDE_SPECS = [
     dict(dim=2, lt=8, lx=24, ly=1, n=2, beta=BC2, l=17, n_step=6, n_traj=5, seed=36),
     dict(dim=3, lt=4, lx=24, ly=4, n=3, beta=BC3, l=10, n_step=8, n_traj=3, seed=37, subsets=True),
     dict(dim=3, lt=6, lx=24, ly=2, n=2, beta=0.25, l=23, n_step=4, n_traj=4, seed=38, spin_format=1, reverse=True),
+    dict(dim=2, lt=8, lx=64, ly=1, n=2, beta=BC2, l=45, n_step=5, n_traj=3, seed=39, whole=True),
 ]
 
 
@@ -249,6 +259,30 @@ def test_rows_wider_than_a_workgroup_stream():
     assert np.array_equal(j.work(), I_or)
     assert np.array_equal(j.spins(), sp_or)
     j.close()
+
+
+def test_whole_region_of_one_column_is_the_increment_from_no_cut():
+    """A(0) -> A(1): the whole-region protocol with l = 1 and the c-function
+    protocol with l = 0 are the same geometry, so the GPU gives the same bits."""
+    kw = dict(dim=2, lt=8, lx=16, ly=1, n=2, beta=BC2, n_step=12, n_traj=6, seed=61)
+    a, b = ee.Job(ee.JobSpec(l=1, whole=True, **kw)), ee.Job(ee.JobSpec(l=0, **kw))
+    for j in (a, b):
+        j.thermalize(4)
+        j.run_protocol()
+    assert np.array_equal(a.work(), b.work()) and np.array_equal(a.spins(), b.spins())
+    a.close()
+    b.close()
+
+
+def test_whole_region_descriptions_are_checked():
+    base = dict(dim=2, lt=8, lx=8, ly=1, n=2, beta=0.4, n_step=4, n_traj=2, seed=1, whole=True)
+    for l in (0, 9):
+        with pytest.raises(ee.EEError) as e:
+            ee.ee_job_footprint(ee.JobSpec(l=l, **base).desc())
+        assert e.value.status == ee.EE_EINVAL
+    with pytest.raises(ee.EEError):
+        ee.ee_job_footprint(ee.JobSpec(**dict(base, dim=3, ly=2, l=3, subsets=True)).desc())
+    assert ee.ee_job_footprint(ee.JobSpec(l=8, **base).desc()) > 0
 
 
 def test_launch_flags_are_checked():

@@ -83,6 +83,23 @@ def test_3d_protocol2_matches_transfer_matrix():
         check(r, exact_dF(3, lt, lx, ly, 2, l, BC3), n_t)
 
 
+@pytest.mark.parametrize("n_rep", [2, 3])
+def test_whole_region_gives_renyi_entropy(n_rep):
+    """Whole-region protocol (Sec. 3): Delta F = (n-1) S_n(l) directly,
+    against the transfer matrix, Delta F* = log Z_n(0) - log Z_n(l)."""
+    lt, n_t, N = 16, 4096, 200
+    lx = 6 if n_rep == 2 else 4  # transfer-matrix plane n*lx <= 12 spins
+    ls = (1, lx // 2, lx)
+    specs = [ee.JobSpec(dim=2, lt=lt, lx=lx, ly=1, n=n_rep, beta=BC2, l=l, n_step=N, n_traj=n_t, seed=200 + l,
+                        whole=True) for l in ls]
+    print(f"[gpu] whole-region protocol {lt}x{lx}, n = {n_rep}", file=sys.stderr, flush=True)
+    res = run_jobs(specs, 200)
+    z0 = ex.log_z_transfer(ex.Lattice(2, lt, lx, 1, n_rep, 0), BC2, glued_upto=0, ramp=False)
+    for l, r in zip(ls, res):
+        zl = ex.log_z_transfer(ex.Lattice(2, lt, lx, 1, n_rep, l), BC2, glued_upto=l, ramp=False)
+        check(r, z0 - zl, n_t)
+
+
 def test_direct_and_reverse_protocols_agree():
     """<e^-W>_dir = 1/<e^-W>_rev (App. A): dF_forward = -dF_reverse."""
     kw = dict(dim=2, lt=32, lx=16, ly=1, n=2, beta=BC2, l=5, n_step=200, n_traj=2048)
