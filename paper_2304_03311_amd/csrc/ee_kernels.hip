@@ -11,7 +11,8 @@
 //   and only a tie (probability 2^-16) draws the low 16 bits from a second
 //   call.  In batch mode the workgroups are persistent and pull work units
 //   (job, block of trajectories) from a device queue.
-// estimate_kernel: Jarzynski estimator of one job per workgroup (App. A):
+// estimate_kernel: Jarzynski estimator of one job per workgroup (App. A),
+//   with wave-shuffle reductions and scans:
 //   integer max/min/sum of I_j, FP64 sum of exp(beta (I_j - I_max)/N),
 //   log-sum-exp, delete-one jackknife from prefix/suffix sums.
 #include <hip/hip_runtime.h>
@@ -857,25 +858,46 @@ __global__ void queue_reset_kernel(int* queue) {
 // ---------------------------------------------------------------------------
 constexpr int kEstThreads = 256;
 
+constexpr int kEstWaves = kEstThreads / 64;
+
+// Reduction over the block: butterfly shuffles within each 64-lane wave,
+// then the kEstWaves wave results through LDS (sh: kEstWaves entries).
 template <typename T, typename Op>
 __device__ T block_reduce(T v, T* sh, Op op) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = kEstThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) sh[tid] = op(sh[tid], sh[tid + s]);
-    __syncthreads();
-  }
   T r = sh[0];
+#pragma unroll
+  for (int k = 1; k < kEstWaves; ++k) r = op(r, sh[k]);
   __syncthreads();
   return r;
 }
 
+// Exclusive prefix sum over the block in thread order: shuffle scan within
+// each wave, wave totals through LDS (sh: kEstWaves entries).
+__device__ double block_exclusive_scan(double v, double* sh) {
+  const int ln = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double u = __shfl_up(incl, off, 64);
+    if (ln >= off) incl += u;
+  }
+  if (ln == 63) sh[wv] = incl;
+  const double excl_wave = __shfl_up(incl, 1, 64);
+  __syncthreads();
+  double base = 0.0;
+  for (int k = 0; k < wv; ++k) base += sh[k];
+  __syncthreads();
+  return (ln == 0) ? base : base + excl_wave;
+}
+
 __global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* const* jobtab) {
-  __shared__ double shd[kEstThreads];
-  __shared__ long long shl[kEstThreads];
-  __shared__ double pre[kEstThreads + 1];
-  __shared__ double suf[kEstThreads + 1];
+  __shared__ double shd[kEstWaves];
+  __shared__ long long shl[kEstWaves];
+  __shared__ double csh[kEstThreads];
   const JobDev* J = jobtab[blockIdx.x];
   const int tid = threadIdx.x;
   const int n = J->n_traj;
@@ -908,24 +930,25 @@ __global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* con
   }
   const double s = block_reduce(cs, shd, [](double a, double b) { return a + b; });
   const double s2 = block_reduce(cs2, shd, [](double a, double b) { return a + b; });
-  // exclusive prefix / suffix of the chunk sums (serial over 256 values)
-  shd[tid] = cs;
+  // sums of the chunks before (pre) and after (suf) this thread's, each by
+  // its own scan so that the leave-one-out sums are formed without
+  // subtracting from the total (no cancellation)
+  const double pre = block_exclusive_scan(cs, shd);
+  csh[tid] = cs;
   __syncthreads();
-  if (tid == 0) {
-    pre[0] = 0.0;
-    for (int k = 0; k < kEstThreads; ++k) pre[k + 1] = pre[k] + shd[k];
-    suf[kEstThreads] = 0.0;
-    for (int k = kEstThreads - 1; k >= 0; --k) suf[k] = suf[k + 1] + shd[k];
-  }
+  const double suf = block_exclusive_scan(csh[kEstThreads - 1 - tid], shd);  // over chunks > this one, reversed
   __syncthreads();
+  csh[kEstThreads - 1 - tid] = suf;
+  __syncthreads();
+  const double after0 = csh[tid];
   const double shift = (beta * (double)imax) / N;
   const double dF = -(shift + log(s) - log((double)n));
   double loo_sum = 0.0;
   if (n >= 2) {
-    double after = suf[tid + 1];  // sum over later chunks
+    double after = after0;  // sum over later chunks
     for (int i = hi - 1; i >= lo; --i) {
       const double e = exp((beta * (double)(I[i] - imax)) / N);
-      const double si = (pre[tid] + scratch[i]) + after;  // sum over j != i
+      const double si = (pre + scratch[i]) + after;  // sum over j != i
       after += e;
       const double loo = -(shift + log(si) - log((double)(n - 1)));
       scratch[i] = loo;
