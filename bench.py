@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 32-bit VALU lane-ops/s.
 PEAK_INT_LANE_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_HBM_GBPS = 8000.0           # MI355X HBM3E
+STREAM_BYTES_PER_ATTEMPT = 1.5   # int8 planes streamed from HBM: opposite plane read, own plane read + written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_2d64_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_03311_amd", "csrc", f) for f in ("ee_kernels.hip", "ee_internal.hpp")]
 
@@ -159,8 +161,9 @@ def streaming_run() -> dict:
     job.close()
     return {"workload": "3D 96^3, n=2, n_t=32, N=100, N_therm=10, int8 in HBM", "attempts_per_ns": r.attempts / (dt * 1e9),
             "ms": dt * 1e3, "launches": 2 * 110 + 3,
-            "algorithmic_bytes_per_attempt": 1.5,
-            "hbm_GBps_algorithmic": 1.5 * r.attempts / dt / 1e9}
+            "algorithmic_bytes_per_attempt": STREAM_BYTES_PER_ATTEMPT,
+            "hbm_GBps_algorithmic": STREAM_BYTES_PER_ATTEMPT * r.attempts / dt / 1e9,
+            "hbm_frac": STREAM_BYTES_PER_ATTEMPT * r.attempts / dt / 1e9 / PEAK_HBM_GBPS}
 
 
 def main() -> int:
@@ -263,6 +266,14 @@ def main() -> int:
                      "kernel": "sweep_kernel (persistent)", "kernel_ms": k_avg_s * 1e3,
                      "ops_per_attempt": ops_per_attempt(2),
                      "attempts_per_ns_in_kernel": attempts_per_step / (k_avg_s * 1e9)},
+        # The persistent path keeps every lattice in LDS, so HBM does not bound
+        # it (traffic above).  For comparison, the roofline of a design that
+        # streams the int8 colour planes from HBM each half-sweep (read the
+        # opposite plane once, read and write the own plane: 1.5 B/attempt).
+        "hbm_streamed_equivalent": {
+            "bytes_per_attempt": STREAM_BYTES_PER_ATTEMPT,
+            "attempts_per_ns_at_peak": PEAK_HBM_GBPS / STREAM_BYTES_PER_ATTEMPT,
+            "frac": attempts_per_step / (k_avg_s * 1e9) / (PEAK_HBM_GBPS / STREAM_BYTES_PER_ATTEMPT)},
         "c2_fit_k": curve.get("fit_k"),
         "launch": launch,
     }
