@@ -28,6 +28,13 @@
 namespace ee {
 
 constexpr int kMaxSlots = 16;  // trajectories per workgroup at most
+// The sweep kernels' small tables (unit index, per-slot work sums, threshold
+// table) follow the trajectory slots in dynamic LDS: a launch whose slots
+// take lds_bytes asks for lds_bytes + kSweepTailBytes and passes the
+// tables' word offset.
+constexpr int kSweepTailBytes = 128;
+static_assert((4 + kMaxSlots + 8) * 4 <= kSweepTailBytes, "sweep LDS tables");
+inline int sweep_tail_words(int lds_bytes) { return (lds_bytes + 15) / 16 * 4; }
 constexpr uint32_t kFlagInit = 1u;   // draw the initial spins (else load them)
 constexpr uint32_t kFlagProto = 2u;  // run the N protocol sweeps after n_therm sweeps
 

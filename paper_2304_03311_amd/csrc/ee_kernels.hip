@@ -207,15 +207,6 @@ __device__ __forceinline__ Lane make_lane(const JP& P, int lt_, int T, int W, bo
 
 __device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) { return (a ^ b) + c; }
 
-// One half-sweep of colour c over the lane's rows of one trajectory.
-//   L    the trajectory in LDS (two colour planes)
-//   thr  LDS table: thr[a] = threshold of a bulk/glued site with a
-//        anti-aligned neighbours (2^32-1 for a >= DIM)
-// FULL: lx/2 is a multiple of 4 (no pad bytes, x-neighbours by byte
-// alignment of two words).  UJ: the trajectory index is uniform per wave.
-// W: consecutive words per lane (2 or 4 need FULL and a word count that W
-// divides; 3 needs FULL and rows of exactly three words, so that w = 0 and
-// words 0, 1 share a Philox call while word 2 takes the next one).
 // Ramp position (0..S) of row y when the protocol stands at position pos
 // (0..N): every row follows pos, or (subset protocol) row y moves during
 // steps [y S, (y+1) S).
@@ -295,15 +286,257 @@ __device__ __forceinline__ uint32_t glued_mask(int v) {
   return (ng >= 4) ? 0xFFFFFFFFu : ((1u << (8 * ng)) - 1u);
 }
 
-// pos: protocol position of this sweep; dpos: pos minus the previous
-// position (+1 forward, -1 reverse, 0 while thermalising).
+// The Metropolis update of the sites of one row of colour c that a lane
+// owns (words w .. w+W-1 of the row).
+//   Lc, Lo  the row's own colour plane and the other one (LDS or HBM)
+//   thr     LDS table: thr[a] = threshold of a bulk/glued site with a
+//           anti-aligned neighbours (2^32-1 for a >= DIM)
+//   (r, t, y)  the row; pC, pO  word w of the row in Lc and in Lo
+//   tmo, tpo, ymo, ypo  offsets from pO of the same words in rows t-1,
+//           t+1, y-1 and y+1 (periodic)
+//   c0, c3  Philox counter words 0 and 3 of the row's first call
+//   pos     protocol position of this sweep; dpos  pos minus the previous
+//           position (+1 forward, -1 reverse, 0 while thermalising)
+// FULL: lx/2 is a multiple of 4 (no pad bytes, x-neighbours by byte
+// alignment of two words).  W: consecutive words per lane (2 or 4 need
+// FULL and a word count that W divides; 3 needs FULL and rows of exactly
+// three words, so that w = 0 and words 0, 1 share a Philox call while word
+// 2 takes the next one).  PAR: the row's x parity p = (c + t + y) & 1 when
+// the caller knows it at compile time, else -1.
+template <int DIM, bool FULL, int W, int PAR>
+__device__ __forceinline__ void row_update(const JP& P, const int w, const int wl, const int wr,
+                                           uint32_t* __restrict__ Lc, const uint32_t* __restrict__ Lo,
+                                           const uint32_t* __restrict__ thr, const int c, const uint32_t g,
+                                           const uint32_t j, const int pos, const int dpos, const bool work,
+                                           int& dI, const int r, const int t, const int y,
+                                           uint32_t* __restrict__ pC, const uint32_t* __restrict__ pO,
+                                           const int tmo, const int tpo, const int ymo, const int ypo,
+                                           const uint32_t c0, const uint32_t c3) {
+  static_assert(W == 1 || ((W == 2 || W == 3 || W == 4) && FULL), "several words per lane need whole rows");
+  const int rw = (int)(pO - Lo);
+  constexpr int NC = (W + 1) / 2;  // Philox calls per row: 8 sites each
+  const int G = P.G;
+  const int LyG = P.ly * G;
+  const int ramp_w = P.l >> 3;
+  const int ramp_p = P.l & 1;
+  const int ramp_sh = 8 * ((P.l >> 1) & 3);
+  const int tailsh = 8 * ((P.H - 1) & 3);
+  const uint32_t valid = (!FULL && w == G - 1 && tailsh != 24) ? ((1u << (tailsh + 8)) - 1u) : 0xFFFFFFFFu;
+  const uint32_t fmask = valid & 0x01010101u;  // bit 0 of every real site's byte
+  const uint32_t rshift = (w == G - 1) ? (uint32_t)tailsh : 24u;
+  const int p = (PAR >= 0) ? PAR : ((c + t + y) & 1);  // x parity of this row's sites
+  uint32_t A[W], B[W], S[W], a[W];
+  ld_words<W>(pO, A);
+  if (FULL) {
+    // the sites' x-1 (p = 0) or x+1 (p = 1) neighbours straddle two words
+    const uint32_t E = pO[(p ? wr : wl) - w];
+    const uint32_t sh = p ? 1u : 3u;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const uint32_t nxt = (q + 1 < W) ? A[q + 1] : E;
+      const uint32_t prv = (q > 0) ? A[q - 1] : E;
+      B[q] = __builtin_amdgcn_alignbyte(p ? nxt : A[q], p ? A[q] : prv, sh);
+    }
+  } else {
+    const uint32_t nb = pO[(p ? wr : wl) - w];
+    const uint32_t Br = (A[0] >> 8) | ((nb & 0xFFu) << rshift);
+    const uint32_t Bl = (A[0] << 8) | ((w == 0) ? ((nb >> tailsh) & 0xFFu) : (nb >> 24));
+    B[0] = p ? Br : Bl;
+  }
+  // t -+ 1 neighbours
+  uint32_t Tm[W], Tp[W];
+  ld_words<W>(pC, S);
+  ld_words<W>(pO + tmo, Tm);
+  ld_words<W>(pO + tpo, Tp);
+#pragma unroll
+  for (int q = 0; q < W; ++q) a[q] = xad(A[q], S[q], xad(B[q], S[q], xad(Tm[q], S[q], Tp[q] ^ S[q])));
+  if (DIM == 3) {
+    uint32_t Ym[W], Yp[W];
+    ld_words<W>(pO + ymo, Ym);
+    ld_words<W>(pO + ypo, Yp);
+#pragma unroll
+    for (int q = 0; q < W; ++q) a[q] = xad(Ym[q], S[q], xad(Yp[q], S[q], a[q]));
+  }
+  if (t <= 1 && !P.whole) {
+    // Row next to the cut: for glued columns x < l the temporal partner
+    // across the cut is in replica r+1 (t = 0) or r-1 (t = 1).
+    const int og = glued_row(P, r, t, y) * G + w;
+    const uint32_t t0mask = (t == 0) ? 0xFFFFFFFFu : 0u;
+    uint32_t Tgl[W];
+    ld_words<W>(Lo + og, Tgl);
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const uint32_t Tg = Tgl[q];
+      const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
+      // own-replica partner across the cut: Tp on t = 0, Tm on t = 1
+      const uint32_t Tcut = (Tp[q] & t0mask) | (Tm[q] & ~t0mask);
+      const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
+      a[q] = a[q] - (Tcut ^ S[q]) + (Teff ^ S[q]);
+    }
+  }
+  // Random numbers: one Philox call serves the 8 sites of this row with the
+  // same h >> 3; site i of word q uses the 16-bit half (i & 1) of output
+  // word ob + 2q + (i >> 1).  The decision u <= U with u = 2^16 v + w is
+  // v < U >> 16 unless v equals U >> 16; only then is w (a phase-2 call)
+  // needed.  Sites 0, 1 of word q take the halves of one output word and
+  // sites 2, 3 those of the next, so both sides are compared two at a time
+  // as 16-bit lanes: d = sat(v' - t) with v' = v ^ 0x8000 and
+  // t = (U >> 16) ^ 0x8000 has the sign of v - (U >> 16), and d = 0 marks
+  // a tie.
+  // Call k serves words 2k and 2k+1 of the lane (W >= 2) or, with W = 1,
+  // the lane's word alone, whose fields start at output word ob.
+  const int ob = (W == 1) ? 2 * (w & 1) : 0;
+  uint32_t f[W];
+  uint32_t dmin = 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    // u[0], u[2] arrive as v ^ 0x8000 per field; u[1], u[3] are xored here
+    uint32_t u[4];
+    philox10_x02(c0 + k, g, j, c3, P.key0, P.key1, 0x80008000u, u);
+    u[1] ^= 0x80008000u;
+    u[3] ^= 0x80008000u;
+#pragma unroll
+    for (int q = 2 * k; q < 2 * k + 2 && q < W; ++q) {
+      // bulk/glued sites: t of site i from the byte tables, selected by byte i of a
+      const uint32_t th = __builtin_amdgcn_perm(P.pt_hi1, P.pt_hi0, a[q]);
+      const uint32_t tl = __builtin_amdgcn_perm(P.pt_lo1, P.pt_lo0, a[q]);
+      const int o = (ob + 2 * q) & 3;
+      const uint32_t d01 = sub_sat_s16x2(pick4(u, o), __builtin_amdgcn_perm(th, tl, 0x05010400u));
+      const uint32_t d23 = sub_sat_s16x2(pick4(u, o + 1), __builtin_amdgcn_perm(th, tl, 0x07030602u));
+      dmin = min_u16x2(dmin, min_u16x2(d01, d23));
+      // byte i <- the high byte of site i's difference: its bit 7 is the flip
+      f[q] = __builtin_amdgcn_perm(d23, d01, 0x07050301u);
+    }
+  }
+  if (__builtin_expect(((dmin & 0xFFFFu) == 0) | ((dmin >> 16) == 0), 0)) {
+    // rare (2^-16 per site): decide the tied sites on u = 2^16 v + w; the
+    // phase-1 fields are drawn again rather than kept in registers
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      uint32_t u1[4], u2[4];
+      philox10(c0 + k, g, j, c3, P.key0, P.key1, u1);
+      philox10(c0 + k, g, j, c3 + (1u << 28), P.key0, P.key1, u2);
+#pragma unroll
+      for (int q = 2 * k; q < 2 * k + 2 && q < W; ++q) {
+        const uint32_t a4 = a[q] << 2;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
+                                                                 ((a4 >> (8 * i)) & 0xFFu));
+          const int o = ((ob + 2 * q) & 3) + (i >> 1);
+          if (half16(pick4(u1, o), i & 1) == (th >> 16)) {
+            const uint32_t acc = half16(pick4(u2, o), i & 1) <= (th & 0xFFFFu);
+            f[q] = (f[q] & ~(0xFFu << (8 * i))) | (acc << (8 * i + 7));
+          }
+        }
+      }
+    }
+  }
+  if (t <= 1) {
+    // rows next to the cut: the ramped sites (one column, or with the
+    // whole-region protocol every column x < l)
+    if (!P.whole && p == ramp_p && (unsigned)(ramp_w - w) < (unsigned)W) {
+      // ramped site x = l of a row next to the cut (one lane per row): its
+      // threshold replaces the bulk decision taken above for its byte.
+      // K = s (S a_fix + (S-m) s_intra + m s_inter) in units of beta/S.
+      const int og = glued_row(P, r, t, y) * G + w;
+      const int oc = rw + ((t == 0) ? LyG : -LyG);  // own-replica partner across the cut
+      const int m = row_m(P, y, pos);
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        if (w + q != ramp_w) continue;
+        const uint32_t Tg = Lo[og + q];
+        const uint32_t Tcut = Lo[oc + q];
+        const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
+        const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
+        const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
+        const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
+        const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
+        const uint32_t Ur = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
+        const int ri = ramp_sh >> 3;
+        const int o = ((ob + 2 * q) & 3) + (ri >> 1);
+        uint32_t u1[4];
+        philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
+        const uint32_t vr = half16(pick4(u1, o), ri & 1);
+        uint32_t acc = vr < (Ur >> 16);
+        if (vr == (Ur >> 16)) {
+          uint32_t u2[4];
+          philox10(c0 + (q >> 1), g, j, c3 + (1u << 28), P.key0, P.key1, u2);
+          acc = half16(pick4(u2, o), ri & 1) <= (Ur & 0xFFFFu);
+        }
+        f[q] = (f[q] & ~(0xFFu << ramp_sh)) | (acc << (ramp_sh + 7));
+        if (work) {
+          // the ramped site of colour 0 sees phi_k: its bonds' weights moved
+          // by (m - m_prev), so the D_k term is (m - m_prev) 2 (b - c)
+          const int dm = m - row_m(P, y, pos - dpos);
+          dI += dm * 2 * ((int)bb - (int)cc);
+        }
+      }
+    }
+    if (P.whole && 8 * w + p < P.l) {
+      // whole-region protocol: every site x < l of a row next to the cut is
+      // ramped and none is glued.  Per site K = s (S a_fix + (S-m) s_intra +
+      // m s_inter) from the ramp table, replacing the bulk decision.
+      const int og = glued_row(P, r, t, y) * G + w;
+      const int oc = rw + ((t == 0) ? LyG : -LyG);  // own-replica partner across the cut
+      const int m = row_m(P, y, pos);
+      const uint32_t* __restrict__ Um = P.ramp + m * (8 * DIM);
+      uint32_t Tgl[W], Tcl[W];
+      ld_words<W>(Lo + og, Tgl);
+      ld_words<W>(Lo + oc, Tcl);
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        const uint32_t rm = glued_mask(P.l - p - 8 * (w + q));  // bytes with x < l
+        if (rm == 0) continue;
+        const uint32_t bw = Tcl[q] ^ S[q];  // intra partner anti-aligned (bit 0 of each byte)
+        const uint32_t cw = Tgl[q] ^ S[q];  // inter partner anti-aligned
+        const uint32_t fw = a[q] - bw;      // the 2 dim - 1 fixed neighbours
+        uint32_t u1[4];
+        philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (!((rm >> (8 * i)) & 1u)) continue;
+          const uint32_t fa = (fw >> (8 * i)) & 0xFFu;
+          const uint32_t bb = (bw >> (8 * i)) & 1u;
+          const uint32_t cc = (cw >> (8 * i)) & 1u;
+          const uint32_t Ur = Um[fa * 4 + bb * 2 + cc];
+          const int o = ((ob + 2 * q) & 3) + (i >> 1);
+          const uint32_t vr = half16(pick4(u1, o), i & 1);
+          uint32_t acc = vr < (Ur >> 16);
+          if (vr == (Ur >> 16)) {
+            uint32_t u2[4];
+            philox10(c0 + (q >> 1), g, j, c3 + (1u << 28), P.key0, P.key1, u2);
+            acc = half16(pick4(u2, o), i & 1) <= (Ur & 0xFFFFu);
+          }
+          f[q] = (f[q] & ~(0xFFu << (8 * i))) | (acc << (8 * i + 7));
+        }
+        if (work) {
+          // colour-0 ramped sites see phi_k; each adds (m - m_prev) 2 (b - c)
+          const int dm = m - row_m(P, y, pos - dpos);
+          const uint32_t sel = rm & 0x01010101u;
+          dI += dm * 2 * (__popc(bw & sel) - __popc(cw & sel));
+        }
+      }
+    }
+  }
+  uint32_t Snew[W];
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+    // S ^ ((f >> 7) & fmask) in one three-input op (table 0x78 = a ^ (b & c))
+    Snew[q] = __builtin_amdgcn_bitop3_b32(S[q], f[q] >> 7, fmask, 0x78);
+  }
+  st_words<W>(pC, Snew);
+}
+
+// One half-sweep of colour c over the lane's rows of one trajectory, in the
+// order of the lane map (any map; the streaming path's and the general
+// on-chip one).  L: the trajectory (two colour planes).  UJ: the
+// trajectory index is uniform per wave.
 template <int DIM, bool FULL, bool UJ, int W>
 __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t* __restrict__ L,
                                            const uint32_t* __restrict__ thr, const int c,
                                            const uint32_t g, uint32_t j, const int pos, const int dpos,
                                            const bool work, int& dI) {
-  static_assert(W == 1 || ((W == 2 || W == 3 || W == 4) && FULL), "several words per lane need whole rows");
-  constexpr int NC = (W + 1) / 2;  // Philox calls per row: 8 sites each
   if (UJ) j = __builtin_amdgcn_readfirstlane(j);
   const int G = P.G;
   const int cw = P.n * P.R * G;  // words per colour plane
@@ -313,225 +546,19 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
   const int ltLyG = P.lt * LyG;
   const int ywrap = (P.ly - 1) * G;
   const uint32_t ctr3 = (1u << 28) | (uint32_t)c;
-  const int ramp_w = P.l >> 3;
-  const int ramp_p = P.l & 1;
-  const int ramp_sh = 8 * ((P.l >> 1) & 3);
   const int w = ln.w;
-  const int tailsh = 8 * ((P.H - 1) & 3);
-  const uint32_t valid = (!FULL && w == G - 1 && tailsh != 24) ? ((1u << (tailsh + 8)) - 1u) : 0xFFFFFFFFu;
-  const uint32_t fmask = valid & 0x01010101u;  // bit 0 of every real site's byte
-  const uint32_t rshift = (w == G - 1) ? (uint32_t)tailsh : 24u;
   int r = ln.r0, t = ln.t0, y = ln.y0;
   int rowbase = ln.rowbase0;
   for (int kk = ln.kstart; kk < ln.kend; kk += ln.kstep) {
-    const int p = (c + t + y) & 1;  // x parity of this row's sites
-    uint32_t A[W], B[W], S[W], a[W];
-    ld_words<W>(Lo + rowbase + w, A);
-    if (FULL) {
-      // the sites' x-1 (p = 0) or x+1 (p = 1) neighbours straddle two words
-      const uint32_t E = Lo[rowbase + (p ? ln.wr : ln.wl)];
-      const uint32_t sh = p ? 1u : 3u;
-#pragma unroll
-      for (int q = 0; q < W; ++q) {
-        const uint32_t nxt = (q + 1 < W) ? A[q + 1] : E;
-        const uint32_t prv = (q > 0) ? A[q - 1] : E;
-        B[q] = __builtin_amdgcn_alignbyte(p ? nxt : A[q], p ? A[q] : prv, sh);
-      }
-    } else {
-      const uint32_t nb = Lo[rowbase + (p ? ln.wr : ln.wl)];
-      const uint32_t Br = (A[0] >> 8) | ((nb & 0xFFu) << rshift);
-      const uint32_t Bl = (A[0] << 8) | ((w == 0) ? ((nb >> tailsh) & 0xFFu) : (nb >> 24));
-      B[0] = p ? Br : Bl;
-    }
-    // t -+ 1 neighbours; the periodic wrap adds or removes one replica's rows
-    const int om = rowbase + w - LyG + ((t == 0) ? ltLyG : 0);
-    const int op = rowbase + w + LyG - ((t == P.lt - 1) ? ltLyG : 0);
-    uint32_t Tm[W], Tp[W];
-    ld_words<W>(Lc + rowbase + w, S);
-    ld_words<W>(Lo + om, Tm);
-    ld_words<W>(Lo + op, Tp);
-#pragma unroll
-    for (int q = 0; q < W; ++q) a[q] = xad(A[q], S[q], xad(B[q], S[q], xad(Tm[q], S[q], Tp[q] ^ S[q])));
-    if (DIM == 3) {
-      const int oym = rowbase + ((y == 0) ? ywrap : -G) + w;
-      const int oyp = rowbase + ((y == P.ly - 1) ? -ywrap : G) + w;
-      uint32_t Ym[W], Yp[W];
-      ld_words<W>(Lo + oym, Ym);
-      ld_words<W>(Lo + oyp, Yp);
-#pragma unroll
-      for (int q = 0; q < W; ++q) a[q] = xad(Ym[q], S[q], xad(Yp[q], S[q], a[q]));
-    }
-    if (t <= 1 && !P.whole) {
-      // Row next to the cut: for glued columns x < l the temporal partner
-      // across the cut is in replica r+1 (t = 0) or r-1 (t = 1).
-      const int og = glued_row(P, r, t, y) * G + w;
-      const uint32_t t0mask = (t == 0) ? 0xFFFFFFFFu : 0u;
-      uint32_t Tgl[W];
-      ld_words<W>(Lo + og, Tgl);
-#pragma unroll
-      for (int q = 0; q < W; ++q) {
-        const uint32_t Tg = Tgl[q];
-        const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
-        // own-replica partner across the cut: Tp on t = 0, Tm on t = 1
-        const uint32_t Tcut = (Tp[q] & t0mask) | (Tm[q] & ~t0mask);
-        const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
-        a[q] = a[q] - (Tcut ^ S[q]) + (Teff ^ S[q]);
-      }
-    }
-    // Random numbers: one Philox call serves the 8 sites of this row with the
-    // same h >> 3; site i of word q uses the 16-bit half (i & 1) of output
-    // word ob + 2q + (i >> 1).  The decision u <= U with u = 2^16 v + w is
-    // v < U >> 16 unless v equals U >> 16; only then is w (a phase-2 call)
-    // needed.  Sites 0, 1 of word q take the halves of one output word and
-    // sites 2, 3 those of the next, so both sides are compared two at a time
-    // as 16-bit lanes: d = sat(v' - t) with v' = v ^ 0x8000 and
-    // t = (U >> 16) ^ 0x8000 has the sign of v - (U >> 16), and d = 0 marks
-    // a tie.
-    // Call k serves words 2k and 2k+1 of the lane (W >= 2) or, with W = 1,
-    // the lane's word alone, whose fields start at output word ob.
+    // the periodic wrap in t adds or removes one replica's rows
+    const int tmo = -LyG + ((t == 0) ? ltLyG : 0);
+    const int tpo = LyG - ((t == P.lt - 1) ? ltLyG : 0);
+    const int ymo = (y == 0) ? ywrap : -G;
+    const int ypo = (y == P.ly - 1) ? -ywrap : G;
     const uint32_t c0 = (uint32_t)((t * P.ly + y) * P.G8 + (w >> 1));
-    const uint32_t c3 = ctr3 | ((uint32_t)r << 1);
-    const int ob = (W == 1) ? 2 * (w & 1) : 0;
-    uint32_t f[W];
-    uint32_t dmin = 0xFFFFFFFFu;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      // u[0], u[2] arrive as v ^ 0x8000 per field; u[1], u[3] are xored here
-      uint32_t u[4];
-      philox10_x02(c0 + k, g, j, c3, P.key0, P.key1, 0x80008000u, u);
-      u[1] ^= 0x80008000u;
-      u[3] ^= 0x80008000u;
-#pragma unroll
-      for (int q = 2 * k; q < 2 * k + 2 && q < W; ++q) {
-        // bulk/glued sites: t of site i from the byte tables, selected by byte i of a
-        const uint32_t th = __builtin_amdgcn_perm(P.pt_hi1, P.pt_hi0, a[q]);
-        const uint32_t tl = __builtin_amdgcn_perm(P.pt_lo1, P.pt_lo0, a[q]);
-        const int o = (ob + 2 * q) & 3;
-        const uint32_t d01 = sub_sat_s16x2(pick4(u, o), __builtin_amdgcn_perm(th, tl, 0x05010400u));
-        const uint32_t d23 = sub_sat_s16x2(pick4(u, o + 1), __builtin_amdgcn_perm(th, tl, 0x07030602u));
-        dmin = min_u16x2(dmin, min_u16x2(d01, d23));
-        // byte i <- the high byte of site i's difference: its bit 7 is the flip
-        f[q] = __builtin_amdgcn_perm(d23, d01, 0x07050301u);
-      }
-    }
-    if (__builtin_expect(((dmin & 0xFFFFu) == 0) | ((dmin >> 16) == 0), 0)) {
-      // rare (2^-16 per site): decide the tied sites on u = 2^16 v + w; the
-      // phase-1 fields are drawn again rather than kept in registers
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        uint32_t u1[4], u2[4];
-        philox10(c0 + k, g, j, c3, P.key0, P.key1, u1);
-        philox10(c0 + k, g, j, c3 + (1u << 28), P.key0, P.key1, u2);
-#pragma unroll
-        for (int q = 2 * k; q < 2 * k + 2 && q < W; ++q) {
-          const uint32_t a4 = a[q] << 2;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
-                                                                   ((a4 >> (8 * i)) & 0xFFu));
-            const int o = ((ob + 2 * q) & 3) + (i >> 1);
-            if (half16(pick4(u1, o), i & 1) == (th >> 16)) {
-              const uint32_t acc = half16(pick4(u2, o), i & 1) <= (th & 0xFFFFu);
-              f[q] = (f[q] & ~(0xFFu << (8 * i))) | (acc << (8 * i + 7));
-            }
-          }
-        }
-      }
-    }
-    if (t <= 1) {
-      // rows next to the cut: the ramped sites (one column, or with the
-      // whole-region protocol every column x < l)
-      if (!P.whole && p == ramp_p && (unsigned)(ramp_w - w) < (unsigned)W) {
-        // ramped site x = l of a row next to the cut (one lane per row): its
-        // threshold replaces the bulk decision taken above for its byte.
-        // K = s (S a_fix + (S-m) s_intra + m s_inter) in units of beta/S.
-        const int og = glued_row(P, r, t, y) * G + w;
-        const int oc = rowbase + ((t == 0) ? LyG : -LyG) + w;  // own-replica partner across the cut
-        const int m = row_m(P, y, pos);
-  #pragma unroll
-        for (int q = 0; q < W; ++q) {
-          if (w + q != ramp_w) continue;
-          const uint32_t Tg = Lo[og + q];
-          const uint32_t Tcut = Lo[oc + q];
-          const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
-          const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
-          const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
-          const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
-          const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
-          const uint32_t Ur = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
-          const int ri = ramp_sh >> 3;
-          const int o = ((ob + 2 * q) & 3) + (ri >> 1);
-          uint32_t u1[4];
-          philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
-          const uint32_t vr = half16(pick4(u1, o), ri & 1);
-          uint32_t acc = vr < (Ur >> 16);
-          if (vr == (Ur >> 16)) {
-            uint32_t u2[4];
-            philox10(c0 + (q >> 1), g, j, c3 + (1u << 28), P.key0, P.key1, u2);
-            acc = half16(pick4(u2, o), ri & 1) <= (Ur & 0xFFFFu);
-          }
-          f[q] = (f[q] & ~(0xFFu << ramp_sh)) | (acc << (ramp_sh + 7));
-          if (work) {
-            // the ramped site of colour 0 sees phi_k: its bonds' weights moved
-            // by (m - m_prev), so the D_k term is (m - m_prev) 2 (b - c)
-            const int dm = m - row_m(P, y, pos - dpos);
-            dI += dm * 2 * ((int)bb - (int)cc);
-          }
-        }
-      }
-      if (P.whole && 8 * w + p < P.l) {
-        // whole-region protocol: every site x < l of a row next to the cut is
-        // ramped and none is glued.  Per site K = s (S a_fix + (S-m) s_intra +
-        // m s_inter) from the ramp table, replacing the bulk decision.
-        const int og = glued_row(P, r, t, y) * G + w;
-        const int oc = rowbase + ((t == 0) ? LyG : -LyG) + w;  // own-replica partner across the cut
-        const int m = row_m(P, y, pos);
-        const uint32_t* __restrict__ Um = P.ramp + m * (8 * DIM);
-        uint32_t Tgl[W], Tcl[W];
-        ld_words<W>(Lo + og, Tgl);
-        ld_words<W>(Lo + oc, Tcl);
-  #pragma unroll
-        for (int q = 0; q < W; ++q) {
-          const uint32_t rm = glued_mask(P.l - p - 8 * (w + q));  // bytes with x < l
-          if (rm == 0) continue;
-          const uint32_t bw = Tcl[q] ^ S[q];  // intra partner anti-aligned (bit 0 of each byte)
-          const uint32_t cw = Tgl[q] ^ S[q];  // inter partner anti-aligned
-          const uint32_t fw = a[q] - bw;      // the 2 dim - 1 fixed neighbours
-          uint32_t u1[4];
-          philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
-  #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (!((rm >> (8 * i)) & 1u)) continue;
-            const uint32_t fa = (fw >> (8 * i)) & 0xFFu;
-            const uint32_t bb = (bw >> (8 * i)) & 1u;
-            const uint32_t cc = (cw >> (8 * i)) & 1u;
-            const uint32_t Ur = Um[fa * 4 + bb * 2 + cc];
-            const int o = ((ob + 2 * q) & 3) + (i >> 1);
-            const uint32_t vr = half16(pick4(u1, o), i & 1);
-            uint32_t acc = vr < (Ur >> 16);
-            if (vr == (Ur >> 16)) {
-              uint32_t u2[4];
-              philox10(c0 + (q >> 1), g, j, c3 + (1u << 28), P.key0, P.key1, u2);
-              acc = half16(pick4(u2, o), i & 1) <= (Ur & 0xFFFFu);
-            }
-            f[q] = (f[q] & ~(0xFFu << (8 * i))) | (acc << (8 * i + 7));
-          }
-          if (work) {
-            // colour-0 ramped sites see phi_k; each adds (m - m_prev) 2 (b - c)
-            const int dm = m - row_m(P, y, pos - dpos);
-            const uint32_t sel = rm & 0x01010101u;
-            dI += dm * 2 * (__popc(bw & sel) - __popc(cw & sel));
-          }
-        }
-      }
-    }
-    uint32_t Snew[W];
-#pragma unroll
-    for (int q = 0; q < W; ++q) {
-      // S ^ ((f >> 7) & fmask) in one three-input op (table 0x78 = a ^ (b & c))
-      Snew[q] = __builtin_amdgcn_bitop3_b32(S[q], f[q] >> 7, fmask, 0x78);
-    }
-    st_words<W>(Lc + rowbase + w, Snew);
+    row_update<DIM, FULL, W, -1>(P, w, ln.wl, ln.wr, Lc, Lo, thr, c, g, j, pos, dpos, work, dI, r, t, y,
+                                 Lc + rowbase + w, Lo + rowbase + w, tmo, tpo, ymo, ypo, c0,
+                                 ctr3 | ((uint32_t)r << 1));
     // next row of this lane
     rowbase += ln.step;
     if (DIM == 3) {
@@ -546,6 +573,125 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
     }
     r += ln.dr;
   }
+}
+
+// Parity-major row order (grouped lane map, rows of whole words).  The rows
+// (t, y) of a replica fall into two classes by the parity q of t + y, and in
+// a half-sweep of colour c the sites of the class-q rows have x parity
+// p = c ^ q.  Slot k0 of the B slots of its replica takes the class-q rows
+// m = k0, k0 + B, ... below R/2 of both classes, one row of each class per
+// step: the lanes of a wave meet rows of one class at a time, so p is a
+// compile-time constant of each row's code, and the next rows are a fixed
+// stride further on.
+//   2D: t = 2m + q, so the class-1 row is the row after the class-0 one.
+//   3D, ly dividing B: t = m / (ly/2) and y = 2 (m mod ly/2) + ((t + q) & 1):
+//   both rows share t, their y differ in bit 0, and t moves by 2B/ly (even)
+//   from step to step, so both y stay fixed per lane.
+// The rows of one colour are independent within a half-sweep, so the order
+// changes no result.  LanePM holds what is fixed for a work unit: the
+// lane's first class-0 row (t, word offset rw, Philox counter word 0, y),
+// the offsets d_rw, d_c0 of its class-1 partner, the y of both rows and
+// their y-neighbour offsets; dt is the t stride (uniform).
+struct LanePM {
+  int w, wl, wr, r0, dt;
+  uint32_t c3;  // Philox counter word 3 without the colour bit
+  int t, rw, d_rw;
+  uint32_t c0, d_c0;
+  int y[2], ymo[2], ypo[2];
+};
+
+template <int DIM>
+__device__ __forceinline__ LanePM make_lane_pm(const JP& P, int lt_, int T, int W) {
+  const int GW = P.G / W;
+  const int slot = lt_ / GW;
+  const int B = (T / GW) / P.n;
+  LanePM L;
+  L.w = (lt_ - slot * GW) * W;
+  L.wl = (L.w == 0) ? P.G - 1 : L.w - 1;
+  L.wr = (L.w + W == P.G) ? 0 : L.w + W;
+  L.r0 = slot / B;
+  const int k0 = slot - L.r0 * B;
+  L.dt = (DIM == 2) ? 2 * B : (int)fdiv((uint32_t)(2 * B), P.mLy, P.sLy);
+  L.c3 = (1u << 28) | ((uint32_t)L.r0 << 1);
+  int t, y0, y1;
+  if (DIM == 2) {
+    t = 2 * k0;
+    y0 = y1 = 0;
+  } else {
+    t = (int)fdiv((uint32_t)(2 * k0), P.mLy, P.sLy);
+    y0 = 2 * (k0 - t * (P.ly >> 1)) + (t & 1);
+    y1 = y0 ^ 1;
+  }
+  const int rho0 = t * P.ly + y0;
+  const int rho1 = (DIM == 2) ? rho0 + 1 : t * P.ly + y1;
+  L.t = (L.r0 < P.n) ? t : P.lt;  // a slot past the last replica has no rows
+  L.rw = (L.r0 * P.R + rho0) * P.G + L.w;
+  L.d_rw = (rho1 - rho0) * P.G;
+  L.c0 = (uint32_t)(rho0 * P.G8 + (L.w >> 1));
+  L.d_c0 = (uint32_t)((rho1 - rho0) * P.G8);
+  L.y[0] = y0;
+  L.y[1] = y1;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    L.ymo[q] = (L.y[q] == 0) ? (P.ly - 1) * P.G : -P.G;
+    L.ypo[q] = (L.y[q] == P.ly - 1) ? -(P.ly - 1) * P.G : P.G;
+  }
+  return L;
+}
+
+// Rows of colour C of the lane in parity-major order: class 0 (x parity C)
+// and class 1 (x parity C ^ 1) in each step.
+template <int DIM, int W, int C>
+__device__ __forceinline__ void rows_pm(const JP& P, const LanePM& lp, uint32_t* __restrict__ Lc,
+                                        const uint32_t* __restrict__ Lo, const uint32_t* __restrict__ thr,
+                                        const uint32_t g, const uint32_t j, const int pos, const int dpos,
+                                        const bool work, int& dI) {
+  const int LyG = P.ly * P.G;
+  const int ltLyG = P.lt * LyG;
+  const int drw = lp.dt * LyG;
+  const uint32_t dc0 = (uint32_t)(lp.dt * P.ly * P.G8);
+  const uint32_t c3 = lp.c3 | (uint32_t)C;
+  int t = lp.t;
+  // The two row addresses as LDS byte addresses, opaque to the compiler at
+  // each step (the empty asm statement emits nothing): every access is then
+  // one register plus at most one offset, instead of one induction variable
+  // per access plus the LDS base.
+  typedef __attribute__((address_space(3))) uint32_t lds_u32;
+  uint32_t aC = (uint32_t)(uintptr_t)(lds_u32*)(Lc + lp.rw);
+  uint32_t aO = (uint32_t)(uintptr_t)(const lds_u32*)(Lo + lp.rw);
+  const uint32_t da = 4u * (uint32_t)drw;
+  uint32_t c0 = lp.c0;
+  for (; t < P.lt; t += lp.dt, aC += da, aO += da, c0 += dc0) {
+    asm volatile("" : "+v"(aC), "+v"(aO));
+    uint32_t* __restrict__ pC = (uint32_t*)(lds_u32*)(uintptr_t)aC;
+    const uint32_t* __restrict__ pO = (const uint32_t*)(const lds_u32*)(uintptr_t)aO;
+    // class 0.  2D: t is even, so only the wrap below t = 0 can occur
+    const int wrap_m = (t == 0) ? ltLyG : 0;
+    const int wrap_p = (DIM == 3 && t == P.lt - 1) ? ltLyG : 0;
+    row_update<DIM, true, W, C>(P, lp.w, lp.wl, lp.wr, Lc, Lo, thr, C, g, j, pos, dpos, work, dI, lp.r0, t,
+                                lp.y[0], pC, pO, wrap_m - LyG, LyG - wrap_p, lp.ymo[0], lp.ypo[0], c0, c3);
+    // class 1.  2D: the row t + 1 (odd), whose only possible wrap is above
+    // t + 1 = lt - 1; 3D: the same t
+    const int t1 = (DIM == 2) ? t + 1 : t;
+    const int wrap_m1 = (DIM == 3) ? wrap_m : 0;
+    const int wrap_p1 = (DIM == 3) ? wrap_p : ((t1 == P.lt - 1) ? ltLyG : 0);
+    row_update<DIM, true, W, C ^ 1>(P, lp.w, lp.wl, lp.wr, Lc, Lo, thr, C, g, j, pos, dpos, work, dI, lp.r0,
+                                    t1, lp.y[1], pC + lp.d_rw, pO + lp.d_rw, wrap_m1 - LyG, LyG - wrap_p1,
+                                    lp.ymo[1], lp.ypo[1], c0 + lp.d_c0, c3);
+  }
+}
+
+template <int DIM, bool UJ, int W>
+__device__ __forceinline__ void half_sweep_pm(const JP& P, const LanePM& lp, uint32_t* __restrict__ L,
+                                              const uint32_t* __restrict__ thr, const int c,
+                                              const uint32_t g, uint32_t j, const int pos, const int dpos,
+                                              const bool work, int& dI) {
+  if (UJ) j = __builtin_amdgcn_readfirstlane(j);
+  const int cw = P.n * P.R * P.G;
+  uint32_t* __restrict__ Lc = L + c * cw;
+  const uint32_t* __restrict__ Lo = L + (c ^ 1) * cw;
+  if (c == 0) rows_pm<DIM, W, 0>(P, lp, Lc, Lo, thr, g, j, pos, dpos, work, dI);
+  else rows_pm<DIM, W, 1>(P, lp, Lc, Lo, thr, g, j, pos, dpos, work, dI);
 }
 
 // Initial spins (phase 0 of the Philox streams): +1 iff u < 2^31.
@@ -606,9 +752,12 @@ __device__ void store_spins(const JP& P, const uint32_t* L, uint32_t j, int lt_,
 }
 
 // All sweeps of one work unit: k trajectories of one job, one per LDS slot.
-template <int DIM, bool FULL, bool UJ, int W>
+// PM: the rows in parity-major order (half_sweep_pm), else in the order of
+// the lane map.
+template <int DIM, bool FULL, bool UJ, int W, bool PM>
 __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr, int j0,
                                          int cnt, int kslots, uint32_t flags, int n_therm, int g0) {
+  static_assert(!PM || FULL, "the parity-major order needs rows of whole words");
   const int tid = threadIdx.x;
   const int T = blockDim.x / kslots;
   const int slot = tid / T;
@@ -622,28 +771,43 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
     if (flags & ee::kFlagInit) init_spins(P, L, j, lt_, T);
     else load_spins(P, L, j, lt_, T);
   }
-  const Lane ln = make_lane(P, lt_, T, W, true);
-  const bool on = active && ln.kstart < ln.kend;
+  Lane ln;
+  LanePM lp;
+  bool on = active;
+  if constexpr (PM) {
+    lp = make_lane_pm<DIM>(P, lt_, T, W);
+  } else {
+    ln = make_lane(P, lt_, T, W, true);
+    on = active && ln.kstart < ln.kend;
+  }
   __syncthreads();
 
   int dI = 0;
   uint32_t g = (uint32_t)g0;
   const int pos0 = P.reverse ? P.N : 0;
-  for (int s = 0; s < n_therm; ++s, ++g) {
-    if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 0, g, j, pos0, 0, false, dI);
-    __syncthreads();
-    if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 1, g, j, pos0, 0, false, dI);
-    __syncthreads();
-  }
-  if (flags & ee::kFlagProto) {
-    const int dpos = P.reverse ? -1 : 1;
-    for (int k = 0; k < P.N; ++k, ++g) {
-      const int pos = P.reverse ? P.N - 1 - k : k + 1;
-      if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 0, g, j, pos, dpos, true, dI);
-      __syncthreads();
-      if (on) half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, 1, g, j, pos, dpos, false, dI);
+  const auto half = [&](int c, uint32_t gg, int pos, int dpos, bool work) {
+    if constexpr (PM) half_sweep_pm<DIM, UJ, W>(P, lp, L, s_thr, c, gg, j, pos, dpos, work, dI);
+    else half_sweep<DIM, FULL, UJ, W>(P, ln, L, s_thr, c, gg, j, pos, dpos, work, dI);
+  };
+  // n_therm sweeps at the starting position, then (protocol) the N sweeps
+  // k = 0 .. N-1 at positions k+1 (forward) or N-1-k (reverse); the work
+  // is taken at the colour-0 half of each protocol sweep.  One call site
+  // of the half-sweep keeps the code to one copy of the row update.
+  const bool proto = (flags & ee::kFlagProto) != 0;
+  const int n_sweeps = n_therm + (proto ? P.N : 0);
+  const int dpos_p = P.reverse ? -1 : 1;
+  for (int s = 0; s < n_sweeps; ++s, ++g) {
+    const int k = s - n_therm;
+    const bool in_proto = k >= 0;
+    const int pos = in_proto ? (P.reverse ? P.N - 1 - k : k + 1) : pos0;
+    const int dpos = in_proto ? dpos_p : 0;
+#pragma unroll 1
+    for (int c = 0; c < 2; ++c) {
+      if (on) half(c, g, pos, dpos, in_proto && c == 0);
       __syncthreads();
     }
+  }
+  if (proto) {
     if (dI != 0) atomicAdd(&s_dI[slot], dI);
     __syncthreads();
     if (active && lt_ == 0) P.work[j] = (int64_t)s_dI[slot];
@@ -661,31 +825,53 @@ __device__ __forceinline__ int words_per_lane(const JP& P, int T, int wmax) {
   return ((P.H & 7) == 0 && T / (P.G / 2) >= 1) ? 2 : 1;
 }
 
+// Whether the rows of a unit go in parity-major order: the grouped lane map
+// (at least one row slot per replica) and, in 3D, ly dividing the slots of
+// a replica.  Uniform over the workgroup.
+__device__ __forceinline__ bool use_pm(const JP& P, int T, int W) {
+  const int S = T / (P.G / W);
+  if (S < P.n) return false;
+  const int B = S / P.n;
+  return P.dim == 2 || B % P.ly == 0;
+}
+
+// PMOK: the entry point compiles the parity-major rows (the 4-wave kernel;
+// at 64 VGPRs the row code of two classes per step does not fit).
+template <int DIM, bool UJ, int W, bool PMOK>
+__device__ __forceinline__ void run_unit_full(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr, int j0,
+                                              int cnt, int kslots, uint32_t flags, int n_therm, int g0) {
+  if (PMOK && use_pm(P, blockDim.x / kslots, W))
+    run_unit<DIM, true, UJ, W, true>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else
+    run_unit<DIM, true, UJ, W, false>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+}
+
 template <int DIM, int WMAX>
 __device__ __forceinline__ void run_unit_dispatch(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr,
                                                   int j0, int cnt, int kslots, uint32_t flags, int n_therm,
                                                   int g0) {
+  constexpr bool PMOK = WMAX >= 4;
   const int T = blockDim.x / kslots;
   const bool full = (P.H & 3) == 0;
   const bool uj = (T & 63) == 0;
   const int wpl = words_per_lane(P, T, WMAX);
   if constexpr (WMAX >= 4) {
     if (wpl == 4) {
-      if (uj) run_unit<DIM, true, true, 4>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-      else run_unit<DIM, true, false, 4>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      if (uj) run_unit_full<DIM, true, 4, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      else run_unit_full<DIM, false, 4, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
       return;
     }
     if (wpl == 3) {
-      if (uj) run_unit<DIM, true, true, 3>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-      else run_unit<DIM, true, false, 3>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      if (uj) run_unit_full<DIM, true, 3, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      else run_unit_full<DIM, false, 3, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
       return;
     }
   }
-  if (wpl == 2 && uj) run_unit<DIM, true, true, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else if (wpl == 2) run_unit<DIM, true, false, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else if (full && uj) run_unit<DIM, true, true, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else if (full) run_unit<DIM, true, false, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else run_unit<DIM, false, false, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  if (wpl == 2 && uj) run_unit_full<DIM, true, 2, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else if (wpl == 2) run_unit_full<DIM, false, 2, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else if (full && uj) run_unit_full<DIM, true, 1, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else if (full) run_unit_full<DIM, false, 1, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  else run_unit<DIM, false, false, 1, false>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
 }
 
 // Per-job mode (units == nullptr): workgroup b runs trajectories
@@ -693,14 +879,27 @@ __device__ __forceinline__ void run_unit_dispatch(const JP& P, uint32_t* lds, in
 // workgroups draw units from the queue until it is empty.  The dimension of
 // each unit's job selects the 2D or 3D sweep (uniform per workgroup).
 // WMAX: the widest lane (words per lane) the entry point compiles.
+// tail: word offset, in the dynamic LDS, of the workgroup's small tables
+// (unit index, per-slot work sums, threshold table), which follow the
+// trajectory slots.  The kernel has no static LDS, so the slots start at
+// LDS address 0 and the row addresses need no base added.
 template <int WMAX>
 __device__ __forceinline__ void sweep_body(const JobDev* single_job, int single_k, const Unit* units, int n_units,
                                            int* queue, const JobDev* const* jobtab, uint32_t flags, int n_therm,
-                                           int g0) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ int s_unit;
-  __shared__ int s_dI[ee::kMaxSlots];
-  __shared__ uint32_t s_thr[8];
+                                           int g0, int tail) {
+  extern __shared__ __align__(16) uint32_t lds_raw[];
+  // The LDS base as an opaque scalar register value rather than the
+  // (link-time) address of the array: the compiler then folds it into the
+  // row address induction variables instead of adding it at every access.
+  // The empty asm statement only hides the value's origin; it emits nothing.
+  typedef __attribute__((address_space(3))) uint32_t lds_u32;
+  uint32_t lds_addr = (uint32_t)(uintptr_t)(lds_u32*)lds_raw;
+  asm volatile("" : "+s"(lds_addr));
+  uint32_t* const lds = (uint32_t*)(lds_u32*)(uintptr_t)lds_addr;
+  int* const s_tab = reinterpret_cast<int*>(lds + tail);
+  int& s_unit = s_tab[0];
+  int* const s_dI = s_tab + 4;
+  uint32_t* const s_thr = reinterpret_cast<uint32_t*>(s_dI + ee::kMaxSlots);
   const int tid = threadIdx.x;
   for (int iter = 0;; ++iter) {
     const JobDev* J;
@@ -733,8 +932,8 @@ __device__ __forceinline__ void sweep_body(const JobDev* single_job, int single_
 // Up to 8 waves per SIMD (64 VGPRs), one or two words per lane.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
 sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_units, int* queue,
-             const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0) {
-  sweep_body<2>(single_job, single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
+             const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0, int tail) {
+  sweep_body<2>(single_job, single_k, units, n_units, queue, jobtab, flags, n_therm, g0, tail);
 }
 
 // Up to 4 waves per SIMD (128 VGPRs) and up to four words per lane: the
@@ -742,8 +941,8 @@ sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_un
 // whose LDS use already holds a CU to 4 waves per SIMD or fewer.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
 sweep_kernel_wide(const JobDev* single_job, int single_k, const Unit* units, int n_units, int* queue,
-                  const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0) {
-  sweep_body<4>(single_job, single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
+                  const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0, int tail) {
+  sweep_body<4>(single_job, single_k, units, n_units, queue, jobtab, flags, n_therm, g0, tail);
 }
 
 // ---------------------------------------------------------------------------
@@ -989,7 +1188,8 @@ extern "C" {
 int ee_k_max_lds_bytes() { return 160 * 1024 - 256; }
 
 static hipError_t set_lds_attr(const void* fn) {
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, ee_k_max_lds_bytes());
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             ee_k_max_lds_bytes() + ee::kSweepTailBytes);
 }
 
 int ee_k_sweep_kernel_ptr(int wide, const void** fn) {
@@ -1011,12 +1211,14 @@ int ee_k_launch_sweep(int wide, const ee::JobDev* single_job, int single_k, cons
   const void* fn = nullptr;
   hipError_t e = (hipError_t)ee_k_sweep_kernel_ptr(wide, &fn);
   if (e != hipSuccess) return (int)e;
+  const int tail = ee::sweep_tail_words(lds_bytes);
+  const int bytes = lds_bytes + ee::kSweepTailBytes;
   if (wide)
-    hipLaunchKernelGGL(sweep_kernel_wide, dim3(grid), dim3(block), lds_bytes, (hipStream_t)stream, single_job,
-                       single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
+    hipLaunchKernelGGL(sweep_kernel_wide, dim3(grid), dim3(block), bytes, (hipStream_t)stream, single_job,
+                       single_k, units, n_units, queue, jobtab, flags, n_therm, g0, tail);
   else
-    hipLaunchKernelGGL(sweep_kernel, dim3(grid), dim3(block), lds_bytes, (hipStream_t)stream, single_job,
-                       single_k, units, n_units, queue, jobtab, flags, n_therm, g0);
+    hipLaunchKernelGGL(sweep_kernel, dim3(grid), dim3(block), bytes, (hipStream_t)stream, single_job,
+                       single_k, units, n_units, queue, jobtab, flags, n_therm, g0, tail);
   return (int)hipGetLastError();
 }
 

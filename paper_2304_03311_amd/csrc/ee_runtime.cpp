@@ -328,7 +328,9 @@ int pick_wide(uint32_t launch_flags, int block, int lds) {
   const void* fn = nullptr;
   if (ee_k_sweep_kernel_ptr(0, &fn) != 0) return 0;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess || per_cu < 1) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds + ee::kSweepTailBytes) != hipSuccess ||
+      per_cu < 1)
+    return 0;
   const int waves_per_simd = per_cu * ((block + 63) / 64) / 4;  // 4 SIMDs per CU
   return waves_per_simd <= 4 ? 1 : 0;
 }
@@ -409,7 +411,7 @@ ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launc
   int rc = ee_k_sweep_kernel_ptr(P->wide, &fn);
   if (rc != 0) { delete P; return fail(EE_EHIP, "kernel attribute: %s", hipGetErrorString((hipError_t)rc)); }
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, P->block, P->lds);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, P->block, P->lds + ee::kSweepTailBytes);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   const DeviceInfo di = device_info();
   P->grid = cfg.grid_blocks > 0 ? cfg.grid_blocks : di.cus * per_cu;
@@ -461,11 +463,12 @@ ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launc
     const ee::JobDev* const* jt = P->dev_jobtab;
     uint32_t fl = ee::kFlagInit | ee::kFlagProto;
     int nt = n_therm, g0 = 0;
-    void* a_sweep[] = {&sj, &sk, &un, &nu, &q, &jt, &fl, &nt, &g0};
+    int tail = ee::sweep_tail_words(P->lds);
+    void* a_sweep[] = {&sj, &sk, &un, &nu, &q, &jt, &fl, &nt, &g0, &tail};
     kp.func = const_cast<void*>(fn);
     kp.gridDim = dim3(P->grid);
     kp.blockDim = dim3(P->block);
-    kp.sharedMemBytes = P->lds;
+    kp.sharedMemBytes = P->lds + ee::kSweepTailBytes;
     kp.kernelParams = a_sweep;
     if (e == hipSuccess) e = hipGraphAddKernelNode(&n_sweep, g, &n_ev0, 1, &kp);
     if (e == hipSuccess) e = hipGraphAddEventRecordNode(&n_ev1, g, &n_sweep, 1, P->ev_stop);
