@@ -182,7 +182,7 @@ def main() -> int:
                     help="run only the HBM-streaming measurement (3D 96^3) and print its JSON (profiled runs)")
     ap.add_argument("--launch", default=None,
                     help='launch shape as JSON (ee_launch_cfg fields), e.g. \'{"block_threads": 256, '
-                         '"lds_bytes": 54272, "flags": 2}\'; replaces the tuner (used for profiled runs)')
+                         '"lds_bytes": 54272}\'; replaces the tuner (used for profiled runs)')
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device-to-device once (HBM counter calibration)")
     args = ap.parse_args()

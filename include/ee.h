@@ -209,15 +209,6 @@ typedef struct {
  * spins stay in HBM and every half-sweep is one launch over all
  * trajectories, with bit-identical results. */
 #define EE_LAUNCH_STREAMING 1u
-/* ee_launch_cfg.flags: which compiled sweep kernel runs an on-chip launch.
- * EE_LAUNCH_WIDE: the 4-wave-per-SIMD kernel (128 VGPRs), whose lanes take
- * up to four words (16 sites) of a row; EE_LAUNCH_NARROW: the 8-wave kernel
- * (64 VGPRs), one or two words per lane.  Neither: the wide kernel when the
- * launch's LDS use already holds a CU to at most 4 waves per SIMD, else the
- * narrow one.  Setting both is EE_EINVAL.  Results are bit-identical. */
-#define EE_LAUNCH_WIDE 2u
-#define EE_LAUNCH_NARROW 4u
-
 /* ee_batch_run with an explicit launch shape (NULL = defaults). */
 ee_status ee_batch_run_cfg(ee_job* const* jobs, int32_t count, int32_t n_therm,
                            const ee_launch_cfg* cfg, void* hip_stream);

@@ -22,17 +22,15 @@ from . import ee
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_launch.json")
 
-# block size x LDS budget per workgroup x sweep kernel (the 8-wave narrow
-# one, or the 4-wave wide one with up to 16 sites per lane and row).  The
-# small shapes (a wave or two, an LDS budget of a few trajectories) spread
-# latency-bound sets of small lattices over more CUs.
+# block size x LDS budget per workgroup.  The small shapes (a wave or two,
+# an LDS budget of a few trajectories) spread latency-bound sets of small
+# lattices over more CUs.
 CANDIDATES = [
-    {"block_threads": b, "lds_bytes": lds, "grid_blocks": 0, "use_graph": 1, "flags": kern}
+    {"block_threads": b, "lds_bytes": lds, "grid_blocks": 0, "use_graph": 1, "flags": 0}
     for blocks, ldss in (((256, 512, 1024), (40 * 1024, 53 * 1024, 80 * 1024, 160 * 1024 - 256)),
                          ((64, 128), (1024, 2048, 4096)))
     for b in blocks
     for lds in ldss
-    for kern in (ee.EE_LAUNCH_NARROW, ee.EE_LAUNCH_WIDE)
 ]
 
 

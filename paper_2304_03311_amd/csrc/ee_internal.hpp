@@ -83,19 +83,16 @@ inline Magic make_magic(uint32_t d) {
 
 // Launch helpers implemented in ee_kernels.hip.
 extern "C" {
-// wide: 0 = the 8-wave sweep kernel (one or two words per lane), 1 = the
-// 4-wave one (up to four words per lane).
-int ee_k_launch_sweep(int wide, const ee::JobDev* single_job, int single_k, const ee::Unit* units,
-                      int n_units, int* queue, const ee::JobDev* const* jobtab, uint32_t flags,
-                      int n_therm, int g0, int grid, int block, int lds_bytes, void* stream);
+int ee_k_launch_sweep(const ee::JobDev* single_job, int single_k, const ee::Unit* units, int n_units, int* queue,
+                      const ee::JobDev* const* jobtab, uint32_t flags, int n_therm, int g0, int grid, int block,
+                      int lds_bytes, void* stream);
 int ee_k_launch_queue_reset(int* queue, void* stream);
 int ee_k_launch_estimate(const ee::JobDev* const* jobtab, int count, void* stream);
-int ee_k_sweep_kernel_ptr(int wide, const void** fn);
+int ee_k_sweep_kernel_ptr(const void** fn);
 int ee_k_queue_reset_ptr(const void** fn);
 int ee_k_estimate_ptr(const void** fn);
 int ee_k_max_lds_bytes();
-// wide: 1 = the 4-wave streaming kernel (up to four words per lane).
-int ee_k_launch_stream_sweep(int wide, const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos, int dpos,
+int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos, int dpos,
                              int work, void* stream);
 int ee_k_launch_stream_init(const ee::JobDev* job, int n_traj, int lanes, void* stream);
 int ee_k_launch_zero_work(const ee::JobDev* job, int n_traj, void* stream);

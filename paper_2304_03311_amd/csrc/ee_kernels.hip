@@ -16,6 +16,7 @@
 //   integer max/min/sum of I_j, FP64 sum of exp(beta (I_j - I_max)/N),
 //   log-sum-exp, delete-one jackknife from prefix/suffix sums.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "ee_internal.hpp"
 
@@ -207,6 +208,15 @@ __device__ __forceinline__ Lane make_lane(const JP& P, int lt_, int T, int W, bo
 
 __device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) { return (a ^ b) + c; }
 
+// (a ^ b) + c as one v_xad_u32.  Written out because the compiler splits a
+// chain of them into separate xors and three-input adds (six instructions
+// for the four neighbours of a word instead of four).
+__device__ __forceinline__ uint32_t xad_op(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm("v_xad_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
 // Ramp position (0..S) of row y when the protocol stands at position pos
 // (0..N): every row follows pos, or (subset protocol) row y moves during
 // steps [y S, (y+1) S).
@@ -302,8 +312,9 @@ __device__ __forceinline__ uint32_t glued_mask(int v) {
 // FULL and a word count that W divides; 3 needs FULL and rows of exactly
 // three words, so that w = 0 and words 0, 1 share a Philox call while word
 // 2 takes the next one).  PAR: the row's x parity p = (c + t + y) & 1 when
-// the caller knows it at compile time, else -1.
-template <int DIM, bool FULL, int W, int PAR>
+// the caller knows it at compile time, else -1.  CUT: the code for rows next
+// to the cut (t = 0, 1) is compiled in; without it the row must have t > 1.
+template <int DIM, bool FULL, int W, int PAR, bool CUT>
 __device__ __forceinline__ void row_update(const JP& P, const int w, const int wl, const int wr,
                                            uint32_t* __restrict__ Lc, const uint32_t* __restrict__ Lo,
                                            const uint32_t* __restrict__ thr, const int c, const uint32_t g,
@@ -313,13 +324,8 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
                                            const int tmo, const int tpo, const int ymo, const int ypo,
                                            const uint32_t c0, const uint32_t c3) {
   static_assert(W == 1 || ((W == 2 || W == 3 || W == 4) && FULL), "several words per lane need whole rows");
-  const int rw = (int)(pO - Lo);
   constexpr int NC = (W + 1) / 2;  // Philox calls per row: 8 sites each
   const int G = P.G;
-  const int LyG = P.ly * G;
-  const int ramp_w = P.l >> 3;
-  const int ramp_p = P.l & 1;
-  const int ramp_sh = 8 * ((P.l >> 1) & 3);
   const int tailsh = 8 * ((P.H - 1) & 3);
   const uint32_t valid = (!FULL && w == G - 1 && tailsh != 24) ? ((1u << (tailsh + 8)) - 1u) : 0xFFFFFFFFu;
   const uint32_t fmask = valid & 0x01010101u;  // bit 0 of every real site's byte
@@ -349,17 +355,19 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   ld_words<W>(pO + tmo, Tm);
   ld_words<W>(pO + tpo, Tp);
 #pragma unroll
-  for (int q = 0; q < W; ++q) a[q] = xad(A[q], S[q], xad(B[q], S[q], xad(Tm[q], S[q], Tp[q] ^ S[q])));
+  for (int q = 0; q < W; ++q) a[q] = xad_op(A[q], S[q], xad_op(B[q], S[q], xad_op(Tm[q], S[q], Tp[q] ^ S[q])));
   if (DIM == 3) {
     uint32_t Ym[W], Yp[W];
     ld_words<W>(pO + ymo, Ym);
     ld_words<W>(pO + ypo, Yp);
 #pragma unroll
-    for (int q = 0; q < W; ++q) a[q] = xad(Ym[q], S[q], xad(Yp[q], S[q], a[q]));
+    for (int q = 0; q < W; ++q) a[q] = xad_op(Ym[q], S[q], xad_op(Yp[q], S[q], a[q]));
   }
-  if (t <= 1 && !P.whole) {
-    // Row next to the cut: for glued columns x < l the temporal partner
-    // across the cut is in replica r+1 (t = 0) or r-1 (t = 1).
+  // Rows next to the cut (t = 0, 1; compiled in with CUT): for glued
+  // columns x < l the temporal partner across the cut is in replica r+1
+  // (t = 0) or r-1 (t = 1).
+  const bool cutrow = CUT && t <= 1;
+  if (cutrow && !P.whole) {
     const int og = glued_row(P, r, t, y) * G + w;
     const uint32_t t0mask = (t == 0) ? 0xFFFFFFFFu : 0u;
     uint32_t Tgl[W];
@@ -384,9 +392,11 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   // t = (U >> 16) ^ 0x8000 has the sign of v - (U >> 16), and d = 0 marks
   // a tie.
   // Call k serves words 2k and 2k+1 of the lane (W >= 2) or, with W = 1,
-  // the lane's word alone, whose fields start at output word ob.
+  // the lane's word alone, whose fields start at output word ob.  With CUT
+  // the outputs are kept (as v ^ 0x8000 per field) for the ramped sites.
   const int ob = (W == 1) ? 2 * (w & 1) : 0;
   uint32_t f[W];
+  uint32_t U[NC][4];
   uint32_t dmin = 0xFFFFFFFFu;
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
@@ -406,6 +416,10 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
       dmin = min_u16x2(dmin, min_u16x2(d01, d23));
       // byte i <- the high byte of site i's difference: its bit 7 is the flip
       f[q] = __builtin_amdgcn_perm(d23, d01, 0x07050301u);
+    }
+    if (CUT) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) U[k][e] = u[e];
     }
   }
   if (__builtin_expect(((dmin & 0xFFFFu) == 0) | ((dmin >> 16) == 0), 0)) {
@@ -432,12 +446,16 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
       }
     }
   }
-  if (t <= 1) {
+  if (cutrow) {
     // rows next to the cut: the ramped sites (one column, or with the
-    // whole-region protocol every column x < l)
-    if (!P.whole && p == ramp_p && (unsigned)(ramp_w - w) < (unsigned)W) {
-      // ramped site x = l of a row next to the cut (one lane per row): its
-      // threshold replaces the bulk decision taken above for its byte.
+    // whole-region protocol every column x < l), decided after the bulk
+    // and tie decisions, which they replace for their bytes
+    const int LyG = P.ly * G;
+    const int rw = (int)(pO - Lo);
+    const int ramp_w = P.l >> 3;
+    const int ramp_sh = 8 * ((P.l >> 1) & 3);
+    if (!P.whole && p == (P.l & 1) && (unsigned)(ramp_w - w) < (unsigned)W) {
+      // ramped site x = l of a row next to the cut (one lane per row).
       // K = s (S a_fix + (S-m) s_intra + m s_inter) in units of beta/S.
       const int og = glued_row(P, r, t, y) * G + w;
       const int oc = rw + ((t == 0) ? LyG : -LyG);  // own-replica partner across the cut
@@ -455,9 +473,7 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
         const uint32_t Ur = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
         const int ri = ramp_sh >> 3;
         const int o = ((ob + 2 * q) & 3) + (ri >> 1);
-        uint32_t u1[4];
-        philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
-        const uint32_t vr = half16(pick4(u1, o), ri & 1);
+        const uint32_t vr = half16(pick4(U[q >> 1], o), ri & 1) ^ 0x8000u;
         uint32_t acc = vr < (Ur >> 16);
         if (vr == (Ur >> 16)) {
           uint32_t u2[4];
@@ -491,8 +507,6 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
         const uint32_t bw = Tcl[q] ^ S[q];  // intra partner anti-aligned (bit 0 of each byte)
         const uint32_t cw = Tgl[q] ^ S[q];  // inter partner anti-aligned
         const uint32_t fw = a[q] - bw;      // the 2 dim - 1 fixed neighbours
-        uint32_t u1[4];
-        philox10(c0 + (q >> 1), g, j, c3, P.key0, P.key1, u1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           if (!((rm >> (8 * i)) & 1u)) continue;
@@ -501,7 +515,7 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
           const uint32_t cc = (cw >> (8 * i)) & 1u;
           const uint32_t Ur = Um[fa * 4 + bb * 2 + cc];
           const int o = ((ob + 2 * q) & 3) + (i >> 1);
-          const uint32_t vr = half16(pick4(u1, o), i & 1);
+          const uint32_t vr = half16(pick4(U[q >> 1], o), i & 1) ^ 0x8000u;
           uint32_t acc = vr < (Ur >> 16);
           if (vr == (Ur >> 16)) {
             uint32_t u2[4];
@@ -556,7 +570,7 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
     const int ymo = (y == 0) ? ywrap : -G;
     const int ypo = (y == P.ly - 1) ? -ywrap : G;
     const uint32_t c0 = (uint32_t)((t * P.ly + y) * P.G8 + (w >> 1));
-    row_update<DIM, FULL, W, -1>(P, w, ln.wl, ln.wr, Lc, Lo, thr, c, g, j, pos, dpos, work, dI, r, t, y,
+    row_update<DIM, FULL, W, -1, true>(P, w, ln.wl, ln.wr, Lc, Lo, thr, c, g, j, pos, dpos, work, dI, r, t, y,
                                  Lc + rowbase + w, Lo + rowbase + w, tmo, tpo, ymo, ypo, c0,
                                  ctr3 | ((uint32_t)r << 1));
     // next row of this lane
@@ -668,16 +682,25 @@ __device__ __forceinline__ void rows_pm(const JP& P, const LanePM& lp, uint32_t*
     // class 0.  2D: t is even, so only the wrap below t = 0 can occur
     const int wrap_m = (t == 0) ? ltLyG : 0;
     const int wrap_p = (DIM == 3 && t == P.lt - 1) ? ltLyG : 0;
-    row_update<DIM, true, W, C>(P, lp.w, lp.wl, lp.wr, Lc, Lo, thr, C, g, j, pos, dpos, work, dI, lp.r0, t,
-                                lp.y[0], pC, pO, wrap_m - LyG, LyG - wrap_p, lp.ymo[0], lp.ypo[0], c0, c3);
     // class 1.  2D: the row t + 1 (odd), whose only possible wrap is above
     // t + 1 = lt - 1; 3D: the same t
     const int t1 = (DIM == 2) ? t + 1 : t;
     const int wrap_m1 = (DIM == 3) ? wrap_m : 0;
     const int wrap_p1 = (DIM == 3) ? wrap_p : ((t1 == P.lt - 1) ? ltLyG : 0);
-    row_update<DIM, true, W, C ^ 1>(P, lp.w, lp.wl, lp.wr, Lc, Lo, thr, C, g, j, pos, dpos, work, dI, lp.r0,
-                                    t1, lp.y[1], pC + lp.d_rw, pO + lp.d_rw, wrap_m1 - LyG, LyG - wrap_p1,
-                                    lp.ymo[1], lp.ypo[1], c0 + lp.d_c0, c3);
+    const auto rows = [&](auto cut) {
+      constexpr bool CUT = decltype(cut)::value;
+      row_update<DIM, true, W, C, CUT>(P, lp.w, lp.wl, lp.wr, Lc, Lo, thr, C, g, j, pos, dpos, work, dI, lp.r0,
+                                       t, lp.y[0], pC, pO, wrap_m - LyG, LyG - wrap_p, lp.ymo[0], lp.ypo[0], c0,
+                                       c3);
+      row_update<DIM, true, W, C ^ 1, CUT>(P, lp.w, lp.wl, lp.wr, Lc, Lo, thr, C, g, j, pos, dpos, work, dI,
+                                           lp.r0, t1, lp.y[1], pC + lp.d_rw, pO + lp.d_rw, wrap_m1 - LyG,
+                                           LyG - wrap_p1, lp.ymo[1], lp.ypo[1], c0 + lp.d_c0, c3);
+    };
+    // Both rows of a step are next to the cut or neither is (t <= 1 implies
+    // t1 <= 1 in 2D, t1 = t in 3D).  The code for rows next to the cut runs
+    // only in steps where some lane of the wave has such a row.
+    if (__builtin_amdgcn_ballot_w64(t <= 1) != 0) rows(std::true_type{});
+    else rows(std::false_type{});
   }
 }
 
@@ -816,12 +839,12 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
   __syncthreads();
 }
 
-// Words per lane for a job and slot size of T lanes: the widest W <= wmax
-// (4 or 2) that divides the row's words and still gives every row a lane
-// group; with wmax = 4, rows of exactly three words take W = 3.
-__device__ __forceinline__ int words_per_lane(const JP& P, int T, int wmax) {
-  if (wmax >= 4 && (P.H & 15) == 0 && T / (P.G / 4) >= 1) return 4;
-  if (wmax >= 4 && P.H == 12) return 3;
+// Words per lane for a job and slot size of T lanes: the widest W <= 4
+// that divides the row's words and still gives every row a lane group;
+// rows of exactly three words take W = 3.
+__device__ __forceinline__ int words_per_lane(const JP& P, int T) {
+  if ((P.H & 15) == 0 && T / (P.G / 4) >= 1) return 4;
+  if (P.H == 12) return 3;
   return ((P.H & 7) == 0 && T / (P.G / 2) >= 1) ? 2 : 1;
 }
 
@@ -835,55 +858,50 @@ __device__ __forceinline__ bool use_pm(const JP& P, int T, int W) {
   return P.dim == 2 || B % P.ly == 0;
 }
 
-// PMOK: the entry point compiles the parity-major rows (the 4-wave kernel;
-// at 64 VGPRs the row code of two classes per step does not fit).
-template <int DIM, bool UJ, int W, bool PMOK>
+template <int DIM, bool UJ, int W>
 __device__ __forceinline__ void run_unit_full(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr, int j0,
                                               int cnt, int kslots, uint32_t flags, int n_therm, int g0) {
-  if (PMOK && use_pm(P, blockDim.x / kslots, W))
+  if (use_pm(P, blockDim.x / kslots, W))
     run_unit<DIM, true, UJ, W, true>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
   else
     run_unit<DIM, true, UJ, W, false>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
 }
 
-template <int DIM, int WMAX>
+template <int DIM>
 __device__ __forceinline__ void run_unit_dispatch(const JP& P, uint32_t* lds, int* s_dI, uint32_t* s_thr,
                                                   int j0, int cnt, int kslots, uint32_t flags, int n_therm,
                                                   int g0) {
-  constexpr bool PMOK = WMAX >= 4;
   const int T = blockDim.x / kslots;
   const bool full = (P.H & 3) == 0;
   const bool uj = (T & 63) == 0;
-  const int wpl = words_per_lane(P, T, WMAX);
-  if constexpr (WMAX >= 4) {
-    if (wpl == 4) {
-      if (uj) run_unit_full<DIM, true, 4, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-      else run_unit_full<DIM, false, 4, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+  switch (words_per_lane(P, T)) {
+    case 4:
+      if (uj) run_unit_full<DIM, true, 4>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      else run_unit_full<DIM, false, 4>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
       return;
-    }
-    if (wpl == 3) {
-      if (uj) run_unit_full<DIM, true, 3, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-      else run_unit_full<DIM, false, 3, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+    case 3:
+      if (uj) run_unit_full<DIM, true, 3>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      else run_unit_full<DIM, false, 3>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
       return;
-    }
+    case 2:
+      if (uj) run_unit_full<DIM, true, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      else run_unit_full<DIM, false, 2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      return;
+    default:
+      if (full && uj) run_unit_full<DIM, true, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      else if (full) run_unit_full<DIM, false, 1>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      else run_unit<DIM, false, false, 1, false>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
   }
-  if (wpl == 2 && uj) run_unit_full<DIM, true, 2, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else if (wpl == 2) run_unit_full<DIM, false, 2, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else if (full && uj) run_unit_full<DIM, true, 1, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else if (full) run_unit_full<DIM, false, 1, PMOK>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
-  else run_unit<DIM, false, false, 1, false>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
 }
 
 // Per-job mode (units == nullptr): workgroup b runs trajectories
 // [b*single_k, b*single_k + single_k) of single_job.  Batch mode: persistent
 // workgroups draw units from the queue until it is empty.  The dimension of
 // each unit's job selects the 2D or 3D sweep (uniform per workgroup).
-// WMAX: the widest lane (words per lane) the entry point compiles.
 // tail: word offset, in the dynamic LDS, of the workgroup's small tables
 // (unit index, per-slot work sums, threshold table), which follow the
 // trajectory slots.  The kernel has no static LDS, so the slots start at
 // LDS address 0 and the row addresses need no base added.
-template <int WMAX>
 __device__ __forceinline__ void sweep_body(const JobDev* single_job, int single_k, const Unit* units, int n_units,
                                            int* queue, const JobDev* const* jobtab, uint32_t flags, int n_therm,
                                            int g0, int tail) {
@@ -923,26 +941,19 @@ __device__ __forceinline__ void sweep_body(const JobDev* single_job, int single_
     }
     const JP P = load_jp(J);
     if (uni(J->dim) == 3)
-      run_unit_dispatch<3, WMAX>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      run_unit_dispatch<3>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
     else
-      run_unit_dispatch<2, WMAX>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
+      run_unit_dispatch<2>(P, lds, s_dI, s_thr, j0, cnt, kslots, flags, n_therm, g0);
   }
 }
 
-// Up to 8 waves per SIMD (64 VGPRs), one or two words per lane.
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8)))
+// The sweep kernel: up to 4 waves per SIMD (128 VGPRs) and up to four words
+// per lane, so that the per-row address and loop work is spread over 16
+// sites.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
 sweep_kernel(const JobDev* single_job, int single_k, const Unit* units, int n_units, int* queue,
              const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0, int tail) {
-  sweep_body<2>(single_job, single_k, units, n_units, queue, jobtab, flags, n_therm, g0, tail);
-}
-
-// Up to 4 waves per SIMD (128 VGPRs) and up to four words per lane: the
-// per-row address and loop work is spread over 16 sites.  For launches
-// whose LDS use already holds a CU to 4 waves per SIMD or fewer.
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
-sweep_kernel_wide(const JobDev* single_job, int single_k, const Unit* units, int n_units, int* queue,
-                  const JobDev* const* jobtab, uint32_t flags, int n_therm, int g0, int tail) {
-  sweep_body<4>(single_job, single_k, units, n_units, queue, jobtab, flags, n_therm, g0, tail);
+  sweep_body(single_job, single_k, units, n_units, queue, jobtab, flags, n_therm, g0, tail);
 }
 
 // ---------------------------------------------------------------------------
@@ -984,9 +995,8 @@ __device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int la
   if (dI != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.work[j]), (unsigned long long)(long long)dI);
 }
 
-// Body of the streaming launches: the widest lane width the entry point
-// compiles (WMAX) that the job's rows allow.
-template <int WMAX>
+// Body of the streaming launches: the widest lane width (words per lane)
+// that the job's rows allow.
 __device__ __forceinline__ void stream_body(const JobDev* J, int lanes, int c, uint32_t g, int pos, int dpos,
                                             int work) {
   __shared__ uint32_t s_thr[8];
@@ -996,42 +1006,36 @@ __device__ __forceinline__ void stream_body(const JobDev* J, int lanes, int c, u
     s_thr[threadIdx.x] = (threadIdx.x == 0) ? P.thr0 : (threadIdx.x == 1) ? P.thr1
                        : (threadIdx.x == 2 && dim == 3) ? P.thr2 : 0xFFFFFFFFu;
   __syncthreads();
-  const int wpl = words_per_lane(P, lanes, WMAX);
   const bool full = (P.H & 3) == 0;
-  if constexpr (WMAX >= 4) {
-    if (wpl == 4) {
-      if (dim == 3) stream_half<3, true, 4>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
-      else stream_half<2, true, 4>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+  const bool w = work != 0;
+  switch (words_per_lane(P, lanes)) {
+    case 4:
+      if (dim == 3) stream_half<3, true, 4>(P, s_thr, lanes, c, g, pos, dpos, w);
+      else stream_half<2, true, 4>(P, s_thr, lanes, c, g, pos, dpos, w);
       return;
-    }
-    if (wpl == 3) {
-      if (dim == 3) stream_half<3, true, 3>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
-      else stream_half<2, true, 3>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+    case 3:
+      if (dim == 3) stream_half<3, true, 3>(P, s_thr, lanes, c, g, pos, dpos, w);
+      else stream_half<2, true, 3>(P, s_thr, lanes, c, g, pos, dpos, w);
       return;
-    }
-  }
-  if (dim == 3) {
-    if (wpl == 2) stream_half<3, true, 2>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
-    else if (full) stream_half<3, true, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
-    else stream_half<3, false, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
-  } else {
-    if (wpl == 2) stream_half<2, true, 2>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
-    else if (full) stream_half<2, true, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
-    else stream_half<2, false, 1>(P, s_thr, lanes, c, g, pos, dpos, work != 0);
+    case 2:
+      if (dim == 3) stream_half<3, true, 2>(P, s_thr, lanes, c, g, pos, dpos, w);
+      else stream_half<2, true, 2>(P, s_thr, lanes, c, g, pos, dpos, w);
+      return;
+    default:
+      if (dim == 3) {
+        if (full) stream_half<3, true, 1>(P, s_thr, lanes, c, g, pos, dpos, w);
+        else stream_half<3, false, 1>(P, s_thr, lanes, c, g, pos, dpos, w);
+      } else {
+        if (full) stream_half<2, true, 1>(P, s_thr, lanes, c, g, pos, dpos, w);
+        else stream_half<2, false, 1>(P, s_thr, lanes, c, g, pos, dpos, w);
+      }
   }
 }
 
-// 8 waves per SIMD, one or two words per lane.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
-stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int pos, int dpos, int work) {
-  stream_body<2>(J, lanes, c, g, pos, dpos, work);
-}
-
-// 4 waves per SIMD (128 VGPRs), up to four words per lane: rows whose
-// half-length is a multiple of 16 sites.
+// 4 waves per SIMD (128 VGPRs), up to four words per lane.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
-stream_sweep_kernel_wide(const JobDev* J, int lanes, int c, uint32_t g, int pos, int dpos, int work) {
-  stream_body<4>(J, lanes, c, g, pos, dpos, work);
+stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int pos, int dpos, int work) {
+  stream_body(J, lanes, c, g, pos, dpos, work);
 }
 
 // Initial spins of every trajectory, written straight to HBM.
@@ -1192,8 +1196,8 @@ static hipError_t set_lds_attr(const void* fn) {
                              ee_k_max_lds_bytes() + ee::kSweepTailBytes);
 }
 
-int ee_k_sweep_kernel_ptr(int wide, const void** fn) {
-  *fn = wide ? reinterpret_cast<const void*>(&sweep_kernel_wide) : reinterpret_cast<const void*>(&sweep_kernel);
+int ee_k_sweep_kernel_ptr(const void** fn) {
+  *fn = reinterpret_cast<const void*>(&sweep_kernel);
   return (int)set_lds_attr(*fn);
 }
 int ee_k_queue_reset_ptr(const void** fn) {
@@ -1205,33 +1209,25 @@ int ee_k_estimate_ptr(const void** fn) {
   return 0;
 }
 
-int ee_k_launch_sweep(int wide, const ee::JobDev* single_job, int single_k, const ee::Unit* units,
-                      int n_units, int* queue, const ee::JobDev* const* jobtab, uint32_t flags,
-                      int n_therm, int g0, int grid, int block, int lds_bytes, void* stream) {
+int ee_k_launch_sweep(const ee::JobDev* single_job, int single_k, const ee::Unit* units, int n_units, int* queue,
+                      const ee::JobDev* const* jobtab, uint32_t flags, int n_therm, int g0, int grid, int block,
+                      int lds_bytes, void* stream) {
   const void* fn = nullptr;
-  hipError_t e = (hipError_t)ee_k_sweep_kernel_ptr(wide, &fn);
+  hipError_t e = (hipError_t)ee_k_sweep_kernel_ptr(&fn);
   if (e != hipSuccess) return (int)e;
   const int tail = ee::sweep_tail_words(lds_bytes);
   const int bytes = lds_bytes + ee::kSweepTailBytes;
-  if (wide)
-    hipLaunchKernelGGL(sweep_kernel_wide, dim3(grid), dim3(block), bytes, (hipStream_t)stream, single_job,
-                       single_k, units, n_units, queue, jobtab, flags, n_therm, g0, tail);
-  else
-    hipLaunchKernelGGL(sweep_kernel, dim3(grid), dim3(block), bytes, (hipStream_t)stream, single_job,
-                       single_k, units, n_units, queue, jobtab, flags, n_therm, g0, tail);
+  hipLaunchKernelGGL(sweep_kernel, dim3(grid), dim3(block), bytes, (hipStream_t)stream, single_job, single_k, units,
+                     n_units, queue, jobtab, flags, n_therm, g0, tail);
   return (int)hipGetLastError();
 }
 
-int ee_k_launch_stream_sweep(int wide, const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos,
-                             int dpos, int work, void* stream) {
+int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c, uint32_t g, int pos, int dpos,
+                             int work, void* stream) {
   const int bx = (lanes + 255) / 256;
   // one-dimensional grid: bx blocks per trajectory, remapped per XCD in the kernel
-  if (wide)
-    hipLaunchKernelGGL(stream_sweep_kernel_wide, dim3(bx * n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c,
-                       g, pos, dpos, work);
-  else
-    hipLaunchKernelGGL(stream_sweep_kernel, dim3(bx * n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c, g,
-                       pos, dpos, work);
+  hipLaunchKernelGGL(stream_sweep_kernel, dim3(bx * n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c, g,
+                     pos, dpos, work);
   return (int)hipGetLastError();
 }
 

@@ -244,7 +244,6 @@ struct Plan {
   ee_launch_cfg cfg{};
   int dim = 0;
   int block = 0, lds = 0, grid = 0, n_units = 0;
-  int wide = 0;  // which sweep kernel (pick_wide)
   void* dev_buf = nullptr;
   int* dev_queue = nullptr;
   const ee::JobDev** dev_jobtab = nullptr;
@@ -286,15 +285,15 @@ bool same_cfg(const ee_launch_cfg& a, const ee_launch_cfg& b) {
          a.grid_blocks == b.grid_blocks && a.use_graph == b.use_graph && a.flags == b.flags;
 }
 
-// Streaming launches with rows of a multiple of 16 sites per colour use the
-// 4-wave kernel with four words per lane.
-bool stream_wide(const ee_job* j) { return (j->L.H & 15) == 0; }
-
 // Lanes per trajectory of the streaming path: every lane walks about 4 rows
-// (measured on 96^3: 4% faster than 8 rows, and faster than 2).
+// (measured on 96^3: 4% faster than 8 rows, and faster than 2).  W: the
+// words per lane the streaming kernel takes for these rows (four for a
+// multiple of 16 sites per colour, three for rows of 12, two for a
+// multiple of 8, else one).
 int stream_lanes(const ee_job* j) {
   const int nrows = j->d.n_replicas * j->L.R;
-  const int W = stream_wide(j) ? 4 : ((j->L.H & 7) == 0) ? 2 : 1;
+  const int H = j->L.H;
+  const int W = ((H & 15) == 0) ? 4 : (H == 12) ? 3 : ((H & 7) == 0) ? 2 : 1;
   const int GW = j->L.G / W;
   const int nrg = std::max(1, (nrows + 3) / 4);
   return nrg * GW;
@@ -302,7 +301,6 @@ int stream_lanes(const ee_job* j) {
 
 ee_status stream_sweeps(ee_job* j, int n_sweeps, bool protocol) {
   const int lanes = stream_lanes(j);
-  const int wide = stream_wide(j) ? 1 : 0;
   const int nt = j->d.n_traj;
   int rc = 0;
   if (protocol) rc = ee_k_launch_zero_work(j->dev_jobdev(), nt, j->stream);
@@ -312,27 +310,11 @@ ee_status stream_sweeps(ee_job* j, int n_sweeps, bool protocol) {
   const int dpos = protocol ? (rev ? -1 : 1) : 0;
   for (int s = 0; s < n_sweeps && rc == 0; ++s, ++g) {
     const int pos = protocol ? (rev ? N - 1 - s : s + 1) : (rev ? N : 0);
-    rc = ee_k_launch_stream_sweep(wide, j->dev_jobdev(), nt, lanes, 0, g, pos, dpos, protocol ? 1 : 0, j->stream);
-    if (rc == 0) rc = ee_k_launch_stream_sweep(wide, j->dev_jobdev(), nt, lanes, 1, g, pos, dpos, 0, j->stream);
+    rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 0, g, pos, dpos, protocol ? 1 : 0, j->stream);
+    if (rc == 0) rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 1, g, pos, dpos, 0, j->stream);
   }
   if (rc) return fail(EE_EHIP, "streaming sweep launch failed: %s", hipGetErrorString((hipError_t)rc));
   return EE_OK;
-}
-
-// Sweep kernel for an on-chip launch of `block` threads and `lds` bytes per
-// workgroup: the forced one, else the wide (4-wave) kernel when the narrow
-// one could not hold more than 4 waves per SIMD with this LDS use anyway.
-int pick_wide(uint32_t launch_flags, int block, int lds) {
-  if (launch_flags & EE_LAUNCH_WIDE) return 1;
-  if (launch_flags & EE_LAUNCH_NARROW) return 0;
-  const void* fn = nullptr;
-  if (ee_k_sweep_kernel_ptr(0, &fn) != 0) return 0;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds + ee::kSweepTailBytes) != hipSuccess ||
-      per_cu < 1)
-    return 0;
-  const int waves_per_simd = per_cu * ((block + 63) / 64) / 4;  // 4 SIMDs per CU
-  return waves_per_simd <= 4 ? 1 : 0;
 }
 
 ee_status launch_sweep_for_job(ee_job* j, uint32_t flags, int n_therm) {
@@ -350,8 +332,8 @@ ee_status launch_sweep_for_job(ee_job* j, uint32_t flags, int n_therm) {
                              2 * device_info().cus);
   const int grid = (j->d.n_traj + k - 1) / k;
   const int lds = k * j->L.traj_words * 4;
-  const int rc = ee_k_launch_sweep(pick_wide(j->cfg.flags, block, lds), j->dev_jobdev(), k, nullptr, 0, nullptr,
-                                   nullptr, flags, n_therm, (int)j->g, grid, block, lds, j->stream);
+  const int rc = ee_k_launch_sweep(j->dev_jobdev(), k, nullptr, 0, nullptr, nullptr, flags, n_therm, (int)j->g, grid,
+                                   block, lds, j->stream);
   if (rc != 0) return fail(EE_EHIP, "sweep kernel launch failed: %s", hipGetErrorString((hipError_t)rc));
   return EE_OK;
 }
@@ -364,10 +346,8 @@ ee_status check_cfg(const ee_launch_cfg* cfg) {
   if (cfg->lds_bytes < 0 || cfg->lds_bytes > ee_k_max_lds_bytes())
     return fail(EE_EINVAL, "lds_bytes must be in [0, %d]", ee_k_max_lds_bytes());
   if (cfg->grid_blocks < 0) return fail(EE_EINVAL, "grid_blocks must be >= 0");
-  if (cfg->flags & ~(EE_LAUNCH_STREAMING | EE_LAUNCH_WIDE | EE_LAUNCH_NARROW))
+  if (cfg->flags & ~EE_LAUNCH_STREAMING)
     return fail(EE_EINVAL, "unknown launch flags 0x%x", cfg->flags);
-  if ((cfg->flags & EE_LAUNCH_WIDE) && (cfg->flags & EE_LAUNCH_NARROW))
-    return fail(EE_EINVAL, "EE_LAUNCH_WIDE and EE_LAUNCH_NARROW exclude each other");
   return EE_OK;
 }
 
@@ -406,9 +386,8 @@ ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launc
   P->lds = lds_need;
   P->n_units = (int)units.size();
   // persistent grid: as many workgroups as fit on the GPU at once
-  P->wide = pick_wide(cfg.flags, P->block, P->lds);
   const void* fn = nullptr;
-  int rc = ee_k_sweep_kernel_ptr(P->wide, &fn);
+  int rc = ee_k_sweep_kernel_ptr(&fn);
   if (rc != 0) { delete P; return fail(EE_EHIP, "kernel attribute: %s", hipGetErrorString((hipError_t)rc)); }
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, P->block, P->lds + ee::kSweepTailBytes);
@@ -494,7 +473,7 @@ ee_status run_plan(Plan* P, hipStream_t stream) {
     int rc = ee_k_launch_queue_reset(P->dev_queue, stream);
     if (rc) return fail(EE_EHIP, "queue reset launch: %s", hipGetErrorString((hipError_t)rc));
     HIP_TRY(hipEventRecord(P->ev_start, stream));
-    rc = ee_k_launch_sweep(P->wide, nullptr, 0, P->dev_units, P->n_units, P->dev_queue, P->dev_jobtab,
+    rc = ee_k_launch_sweep(nullptr, 0, P->dev_units, P->n_units, P->dev_queue, P->dev_jobtab,
                            ee::kFlagInit | ee::kFlagProto, P->n_therm, 0, P->grid, P->block, P->lds, stream);
     if (rc) return fail(EE_EHIP, "persistent sweep launch: %s", hipGetErrorString((hipError_t)rc));
     HIP_TRY(hipEventRecord(P->ev_stop, stream));

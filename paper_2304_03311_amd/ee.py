@@ -21,8 +21,6 @@ EE_FLAG_REVERSE = 1
 EE_FLAG_SUBSETS = 2
 EE_FLAG_WHOLE = 4
 EE_LAUNCH_STREAMING = 1
-EE_LAUNCH_WIDE = 2
-EE_LAUNCH_NARROW = 4
 
 
 class ee_job_desc(ctypes.Structure):
