@@ -176,13 +176,14 @@ def main() -> int:
     ap.add_argument("--per-job", action="store_true", help="also time the per-job launch path")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency) measurement")
     ap.add_argument("--serve-jobs", type=int, default=400)
-    ap.add_argument("--no-tune", action="store_true", help="library default launch shape instead of the tuner's")
+    ap.add_argument("--tune", action="store_true",
+                    help="time the tuner's launch shape for the headline set instead of the fixed one")
     ap.add_argument("--no-configs", action="store_true", help="skip the c1/c3/c4 job sets")
     ap.add_argument("--stream-only", action="store_true",
                     help="run only the HBM-streaming measurement (3D 96^3) and print its JSON (profiled runs)")
     ap.add_argument("--launch", default=None,
                     help='launch shape as JSON (ee_launch_cfg fields), e.g. \'{"block_threads": 256, '
-                         '"lds_bytes": 54272}\'; replaces the tuner (used for profiled runs)')
+                         '"lds_bytes": 54272}\'; replaces the fixed shape')
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device-to-device once (HBM counter calibration)")
     args = ap.parse_args()
@@ -206,7 +207,7 @@ def main() -> int:
     launch = workloads.BENCH_LAUNCH
     if args.launch is not None:
         launch = json.loads(args.launch)
-    elif not args.no_tune:
+    elif args.tune:
         launch = autotune.cached(specs, n_therm) or autotune.tune(specs, n_therm, stream=stream)
     jobs = [ee.Job(s, stream=stream) for s in specs]
     attempts_per_step = sum(s.n_traj * s.sites * (n_therm + s.n_step) for s in specs)

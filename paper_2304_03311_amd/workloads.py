@@ -30,8 +30,12 @@ BETA_C_2D = 0.5 * math.log(1.0 + math.sqrt(2.0))  # Sec. 4
 BETA_3D = 0.2216546                                 # Sec. 5 (beta_c = 0.221654626(5))
 N_THERM = 100
 
-# launch shape the benchmark times when the tuner is off (None = library defaults)
-BENCH_LAUNCH = None
+# launch shape of the headline set (2D 64x64, 64 jobs x 1024 trajectories):
+# one 64-thread workgroup (one wave) per trajectory, which the sweep over
+# the tuner's shapes and more (64..1024 threads, one to sixteen trajectories
+# per workgroup) measured fastest: each wave owns a whole trajectory, so its
+# barriers wait for no other wave
+BENCH_LAUNCH = {"block_threads": 64, "lds_bytes": 8192, "grid_blocks": 0, "use_graph": 1, "flags": 0}
 
 # serving benchmark: size mix of the Poisson stream (tuned to about 60% of the
 # per-job path's measured capacity at 200 jobs/s), resident-job slots and the
