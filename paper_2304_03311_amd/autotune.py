@@ -51,8 +51,8 @@ def cached(specs, n_therm):
     return _load().get(signature(specs, n_therm))
 
 
-def tune(specs: list[ee.JobSpec], n_therm: int, trial_steps: int = 40, trial_therm: int = 8,
-         candidates=None, repeats: int = 2, stream=None, save: bool = True, verbose: bool = False) -> dict:
+def tune(specs: list[ee.JobSpec], n_therm: int, trial_steps: int = 200, trial_therm: int = 20,
+         candidates=None, repeats: int = 3, stream=None, save: bool = True, verbose: bool = False) -> dict:
     """Pick the fastest launch shape for this job set; returns the ee_launch_cfg dict."""
     import torch
     candidates = CANDIDATES if candidates is None else candidates

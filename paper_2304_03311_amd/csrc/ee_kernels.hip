@@ -570,9 +570,15 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
     const int ymo = (y == 0) ? ywrap : -G;
     const int ypo = (y == P.ly - 1) ? -ywrap : G;
     const uint32_t c0 = (uint32_t)((t * P.ly + y) * P.G8 + (w >> 1));
-    row_update<DIM, FULL, W, -1, true>(P, w, ln.wl, ln.wr, Lc, Lo, thr, c, g, j, pos, dpos, work, dI, r, t, y,
-                                 Lc + rowbase + w, Lo + rowbase + w, tmo, tpo, ymo, ypo, c0,
-                                 ctr3 | ((uint32_t)r << 1));
+    const auto row = [&](auto cut) {
+      row_update<DIM, FULL, W, -1, decltype(cut)::value>(P, w, ln.wl, ln.wr, Lc, Lo, thr, c, g, j, pos, dpos, work,
+                                                         dI, r, t, y, Lc + rowbase + w, Lo + rowbase + w, tmo, tpo,
+                                                         ymo, ypo, c0, ctr3 | ((uint32_t)r << 1));
+    };
+    // the code for rows next to the cut runs only where some lane of the
+    // wave has such a row
+    if (__builtin_amdgcn_ballot_w64(t <= 1) != 0) row(std::true_type{});
+    else row(std::false_type{});
     // next row of this lane
     rowbase += ln.step;
     if (DIM == 3) {
@@ -849,13 +855,15 @@ __device__ __forceinline__ int words_per_lane(const JP& P, int T) {
 }
 
 // Whether the rows of a unit go in parity-major order: the grouped lane map
-// (at least one row slot per replica) and, in 3D, ly dividing the slots of
-// a replica.  Uniform over the workgroup.
+// (at least one row slot per replica), fewer row slots B per replica than
+// rows (else half of them would idle there, while the lane-map order gives
+// every row its own lane), and, in 3D, ly dividing B.  Uniform over the
+// workgroup.
 __device__ __forceinline__ bool use_pm(const JP& P, int T, int W) {
   const int S = T / (P.G / W);
   if (S < P.n) return false;
   const int B = S / P.n;
-  return P.dim == 2 || B % P.ly == 0;
+  return B < P.R && (P.dim == 2 || B % P.ly == 0);
 }
 
 template <int DIM, bool UJ, int W>
