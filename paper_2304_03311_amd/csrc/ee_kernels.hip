@@ -392,12 +392,12 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   // t = (U >> 16) ^ 0x8000 has the sign of v - (U >> 16), and d = 0 marks
   // a tie.
   // Call k serves words 2k and 2k+1 of the lane (W >= 2) or, with W = 1,
-  // the lane's word alone, whose fields start at output word ob.  With CUT
-  // the outputs are kept (as v ^ 0x8000 per field) for the ramped sites.
+  // the lane's word alone, whose fields start at output word ob.  The
+  // outputs are kept (as v ^ 0x8000 per field) for tied and ramped sites.
   const int ob = (W == 1) ? 2 * (w & 1) : 0;
   uint32_t f[W];
   uint32_t U[NC][4];
-  uint32_t dmin = 0xFFFFFFFFu;
+  uint32_t dmk[NC];  // per call: minimum of its d's (a zero half marks a tie)
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     // u[0], u[2] arrive as v ^ 0x8000 per field; u[1], u[3] are xored here
@@ -405,6 +405,7 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
     philox10_x02(c0 + k, g, j, c3, P.key0, P.key1, 0x80008000u, u);
     u[1] ^= 0x80008000u;
     u[3] ^= 0x80008000u;
+    dmk[k] = 0xFFFFFFFFu;
 #pragma unroll
     for (int q = 2 * k; q < 2 * k + 2 && q < W; ++q) {
       // bulk/glued sites: t of site i from the byte tables, selected by byte i of a
@@ -413,22 +414,24 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
       const int o = (ob + 2 * q) & 3;
       const uint32_t d01 = sub_sat_s16x2(pick4(u, o), __builtin_amdgcn_perm(th, tl, 0x05010400u));
       const uint32_t d23 = sub_sat_s16x2(pick4(u, o + 1), __builtin_amdgcn_perm(th, tl, 0x07030602u));
-      dmin = min_u16x2(dmin, min_u16x2(d01, d23));
+      dmk[k] = min_u16x2(dmk[k], min_u16x2(d01, d23));
       // byte i <- the high byte of site i's difference: its bit 7 is the flip
       f[q] = __builtin_amdgcn_perm(d23, d01, 0x07050301u);
     }
-    if (CUT) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) U[k][e] = u[e];
-    }
+    for (int e = 0; e < 4; ++e) U[k][e] = u[e];
   }
-  if (__builtin_expect(((dmin & 0xFFFFu) == 0) | ((dmin >> 16) == 0), 0)) {
-    // rare (2^-16 per site): decide the tied sites on u = 2^16 v + w; the
-    // phase-1 fields are drawn again rather than kept in registers
+  uint32_t dmin = dmk[0];
+#pragma unroll
+  for (int k = 1; k < NC; ++k) dmin = min_u16x2(dmin, dmk[k]);
+  const auto tied = [](uint32_t d) { return ((d & 0xFFFFu) == 0) | ((d >> 16) == 0); };
+  if (__builtin_expect(tied(dmin), 0)) {
+    // rare (2^-16 per site): decide the tied sites on u = 2^16 v + w, with
+    // the phase-2 call of only the calls that have a tie
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      uint32_t u1[4], u2[4];
-      philox10(c0 + k, g, j, c3, P.key0, P.key1, u1);
+      if (!tied(dmk[k])) continue;
+      uint32_t u2[4];
       philox10(c0 + k, g, j, c3 + (1u << 28), P.key0, P.key1, u2);
 #pragma unroll
       for (int q = 2 * k; q < 2 * k + 2 && q < W; ++q) {
@@ -438,7 +441,7 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
           const uint32_t th = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(thr) +
                                                                  ((a4 >> (8 * i)) & 0xFFu));
           const int o = ((ob + 2 * q) & 3) + (i >> 1);
-          if (half16(pick4(u1, o), i & 1) == (th >> 16)) {
+          if ((half16(pick4(U[k], o), i & 1) ^ 0x8000u) == (th >> 16)) {
             const uint32_t acc = half16(pick4(u2, o), i & 1) <= (th & 0xFFFFu);
             f[q] = (f[q] & ~(0xFFu << (8 * i))) | (acc << (8 * i + 7));
           }
