@@ -366,20 +366,22 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   // Rows next to the cut (t = 0, 1; compiled in with CUT): for glued
   // columns x < l the temporal partner across the cut is in replica r+1
   // (t = 0) or r-1 (t = 1).
+  // Tgl: the glued partners' words; Tcu: the own-replica partners across
+  // the cut (Tp on t = 0, Tm on t = 1); Tef: the partners counted in a.
   const bool cutrow = CUT && t <= 1;
-  if (cutrow && !P.whole) {
+  uint32_t Tgl[W], Tcu[W], Tef[W];
+  if (cutrow) {
     const int og = glued_row(P, r, t, y) * G + w;
-    const uint32_t t0mask = (t == 0) ? 0xFFFFFFFFu : 0u;
-    uint32_t Tgl[W];
     ld_words<W>(Lo + og, Tgl);
 #pragma unroll
     for (int q = 0; q < W; ++q) {
-      const uint32_t Tg = Tgl[q];
-      const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
-      // own-replica partner across the cut: Tp on t = 0, Tm on t = 1
-      const uint32_t Tcut = (Tp[q] & t0mask) | (Tm[q] & ~t0mask);
-      const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
-      a[q] = a[q] - (Tcut ^ S[q]) + (Teff ^ S[q]);
+      Tcu[q] = (t == 0) ? Tp[q] : Tm[q];
+      Tef[q] = Tcu[q];
+      if (!P.whole) {
+        const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
+        Tef[q] = (Tgl[q] & gm) | (Tcu[q] & ~gm);
+        a[q] = a[q] - (Tcu[q] ^ S[q]) + (Tef[q] ^ S[q]);
+      }
     }
   }
   // Random numbers: one Philox call serves the 8 sites of this row with the
@@ -453,26 +455,18 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
     // rows next to the cut: the ramped sites (one column, or with the
     // whole-region protocol every column x < l), decided after the bulk
     // and tie decisions, which they replace for their bytes
-    const int LyG = P.ly * G;
-    const int rw = (int)(pO - Lo);
     const int ramp_w = P.l >> 3;
     const int ramp_sh = 8 * ((P.l >> 1) & 3);
     if (!P.whole && p == (P.l & 1) && (unsigned)(ramp_w - w) < (unsigned)W) {
       // ramped site x = l of a row next to the cut (one lane per row).
       // K = s (S a_fix + (S-m) s_intra + m s_inter) in units of beta/S.
-      const int og = glued_row(P, r, t, y) * G + w;
-      const int oc = rw + ((t == 0) ? LyG : -LyG);  // own-replica partner across the cut
       const int m = row_m(P, y, pos);
 #pragma unroll
       for (int q = 0; q < W; ++q) {
         if (w + q != ramp_w) continue;
-        const uint32_t Tg = Lo[og + q];
-        const uint32_t Tcut = Lo[oc + q];
-        const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
-        const uint32_t Teff = (Tg & gm) | (Tcut & ~gm);
-        const uint32_t fa = ((a[q] - (Teff ^ S[q])) >> ramp_sh) & 0xFFu;
-        const uint32_t bb = ((Tcut ^ S[q]) >> ramp_sh) & 1u;
-        const uint32_t cc = ((Tg ^ S[q]) >> ramp_sh) & 1u;
+        const uint32_t fa = ((a[q] - (Tef[q] ^ S[q])) >> ramp_sh) & 0xFFu;
+        const uint32_t bb = ((Tcu[q] ^ S[q]) >> ramp_sh) & 1u;
+        const uint32_t cc = ((Tgl[q] ^ S[q]) >> ramp_sh) & 1u;
         const uint32_t Ur = P.ramp[m * (8 * DIM) + fa * 4 + bb * 2 + cc];
         const int ri = ramp_sh >> 3;
         const int o = ((ob + 2 * q) & 3) + (ri >> 1);
@@ -496,18 +490,13 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
       // whole-region protocol: every site x < l of a row next to the cut is
       // ramped and none is glued.  Per site K = s (S a_fix + (S-m) s_intra +
       // m s_inter) from the ramp table, replacing the bulk decision.
-      const int og = glued_row(P, r, t, y) * G + w;
-      const int oc = rw + ((t == 0) ? LyG : -LyG);  // own-replica partner across the cut
       const int m = row_m(P, y, pos);
       const uint32_t* __restrict__ Um = P.ramp + m * (8 * DIM);
-      uint32_t Tgl[W], Tcl[W];
-      ld_words<W>(Lo + og, Tgl);
-      ld_words<W>(Lo + oc, Tcl);
 #pragma unroll
       for (int q = 0; q < W; ++q) {
         const uint32_t rm = glued_mask(P.l - p - 8 * (w + q));  // bytes with x < l
         if (rm == 0) continue;
-        const uint32_t bw = Tcl[q] ^ S[q];  // intra partner anti-aligned (bit 0 of each byte)
+        const uint32_t bw = Tcu[q] ^ S[q];  // intra partner anti-aligned (bit 0 of each byte)
         const uint32_t cw = Tgl[q] ^ S[q];  // inter partner anti-aligned
         const uint32_t fw = a[q] - bw;      // the 2 dim - 1 fixed neighbours
 #pragma unroll
@@ -567,13 +556,14 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
   int r = ln.r0, t = ln.t0, y = ln.y0;
   int rowbase = ln.rowbase0;
   for (int kk = ln.kstart; kk < ln.kend; kk += ln.kstep) {
-    // the periodic wrap in t adds or removes one replica's rows
-    const int tmo = -LyG + ((t == 0) ? ltLyG : 0);
+    // the periodic wrap in t adds or removes one replica's rows; the one
+    // below t = 0 belongs to a row next to the cut (cut variant only)
     const int tpo = LyG - ((t == P.lt - 1) ? ltLyG : 0);
     const int ymo = (y == 0) ? ywrap : -G;
     const int ypo = (y == P.ly - 1) ? -ywrap : G;
     const uint32_t c0 = (uint32_t)((t * P.ly + y) * P.G8 + (w >> 1));
     const auto row = [&](auto cut) {
+      const int tmo = -LyG + ((decltype(cut)::value && t == 0) ? ltLyG : 0);
       row_update<DIM, FULL, W, -1, decltype(cut)::value>(P, w, ln.wl, ln.wr, Lc, Lo, thr, c, g, j, pos, dpos, work,
                                                          dI, r, t, y, Lc + rowbase + w, Lo + rowbase + w, tmo, tpo,
                                                          ymo, ypo, c0, ctr3 | ((uint32_t)r << 1));
@@ -688,16 +678,17 @@ __device__ __forceinline__ void rows_pm(const JP& P, const LanePM& lp, uint32_t*
     asm volatile("" : "+v"(aC), "+v"(aO));
     uint32_t* __restrict__ pC = (uint32_t*)(lds_u32*)(uintptr_t)aC;
     const uint32_t* __restrict__ pO = (const uint32_t*)(const lds_u32*)(uintptr_t)aO;
-    // class 0.  2D: t is even, so only the wrap below t = 0 can occur
-    const int wrap_m = (t == 0) ? ltLyG : 0;
-    const int wrap_p = (DIM == 3 && t == P.lt - 1) ? ltLyG : 0;
+    // class 0.  2D: t is even, so only the wrap below t = 0 can occur.
     // class 1.  2D: the row t + 1 (odd), whose only possible wrap is above
-    // t + 1 = lt - 1; 3D: the same t
+    // t + 1 = lt - 1; 3D: the same t.  The wrap below t = 0 belongs to a
+    // row next to the cut, so only the cut variant has it.
     const int t1 = (DIM == 2) ? t + 1 : t;
-    const int wrap_m1 = (DIM == 3) ? wrap_m : 0;
+    const int wrap_p = (DIM == 3 && t == P.lt - 1) ? ltLyG : 0;
     const int wrap_p1 = (DIM == 3) ? wrap_p : ((t1 == P.lt - 1) ? ltLyG : 0);
     const auto rows = [&](auto cut) {
       constexpr bool CUT = decltype(cut)::value;
+      const int wrap_m = (CUT && t == 0) ? ltLyG : 0;
+      const int wrap_m1 = (DIM == 3) ? wrap_m : 0;
       row_update<DIM, true, W, C, CUT>(P, lp.w, lp.wl, lp.wr, Lc, Lo, thr, C, g, j, pos, dpos, work, dI, lp.r0,
                                        t, lp.y[0], pC, pO, wrap_m - LyG, LyG - wrap_p, lp.ymo[0], lp.ypo[0], c0,
                                        c3);
