@@ -322,7 +322,8 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
                                            int& dI, const int r, const int t, const int y,
                                            uint32_t* __restrict__ pC, const uint32_t* __restrict__ pO,
                                            const int tmo, const int tpo, const int ymo, const int ypo,
-                                           const uint32_t c0, const uint32_t c3) {
+                                           const uint32_t c0, const uint32_t c3, const int og_in = 0,
+                                           const uint32_t* gm_in = nullptr) {
   static_assert(W == 1 || ((W == 2 || W == 3 || W == 4) && FULL), "several words per lane need whole rows");
   constexpr int NC = (W + 1) / 2;  // Philox calls per row: 8 sites each
   const int G = P.G;
@@ -370,15 +371,18 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   // the cut (Tp on t = 0, Tm on t = 1); Tef: the partners counted in a.
   const bool cutrow = CUT && t <= 1;
   uint32_t Tgl[W], Tcu[W], Tef[W];
+  // gmq(q): bytes of word q with x < l (precomputed per lane where the
+  // caller knows the parity at compile time)
+  const auto gmq = [&](int q) { return (PAR >= 0) ? gm_in[q] : glued_mask(P.l - p - 8 * (w + q)); };
   if (cutrow) {
-    const int og = glued_row(P, r, t, y) * G + w;
+    const int og = (PAR >= 0) ? og_in : glued_row(P, r, t, y) * G + w;
     ld_words<W>(Lo + og, Tgl);
 #pragma unroll
     for (int q = 0; q < W; ++q) {
       Tcu[q] = (t == 0) ? Tp[q] : Tm[q];
       Tef[q] = Tcu[q];
       if (!P.whole) {
-        const uint32_t gm = glued_mask(P.l - p - 8 * (w + q));
+        const uint32_t gm = gmq(q);
         Tef[q] = (Tgl[q] & gm) | (Tcu[q] & ~gm);
         a[q] = a[q] - (Tcu[q] ^ S[q]) + (Tef[q] ^ S[q]);
       }
@@ -494,7 +498,7 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
       const uint32_t* __restrict__ Um = P.ramp + m * (8 * DIM);
 #pragma unroll
       for (int q = 0; q < W; ++q) {
-        const uint32_t rm = glued_mask(P.l - p - 8 * (w + q));  // bytes with x < l
+        const uint32_t rm = gmq(q);  // bytes with x < l
         if (rm == 0) continue;
         const uint32_t bw = Tcu[q] ^ S[q];  // intra partner anti-aligned (bit 0 of each byte)
         const uint32_t cw = Tgl[q] ^ S[q];  // inter partner anti-aligned
@@ -605,16 +609,21 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
 // lane's first class-0 row (t, word offset rw, Philox counter word 0, y),
 // the offsets d_rw, d_c0 of its class-1 partner, the y of both rows and
 // their y-neighbour offsets; dt is the t stride (uniform).
+// For the lane's rows next to the cut (if any) it also holds their glued
+// rows' word offsets og and the byte masks gm[p] of the glued columns x < l
+// of its words for x parity p.
 struct LanePM {
   int w, wl, wr, r0, dt;
   uint32_t c3;  // Philox counter word 3 without the colour bit
   int t, rw, d_rw;
   uint32_t c0, d_c0;
   int y[2], ymo[2], ypo[2];
+  int og[2];
+  uint32_t gm[2][4];
 };
 
-template <int DIM>
-__device__ __forceinline__ LanePM make_lane_pm(const JP& P, int lt_, int T, int W) {
+template <int DIM, int W>
+__device__ __forceinline__ LanePM make_lane_pm(const JP& P, int lt_, int T) {
   const int GW = P.G / W;
   const int slot = lt_ / GW;
   const int B = (T / GW) / P.n;
@@ -648,6 +657,11 @@ __device__ __forceinline__ LanePM make_lane_pm(const JP& P, int lt_, int T, int 
   for (int q = 0; q < 2; ++q) {
     L.ymo[q] = (L.y[q] == 0) ? (P.ly - 1) * P.G : -P.G;
     L.ypo[q] = (L.y[q] == P.ly - 1) ? -(P.ly - 1) * P.G : P.G;
+    // the class-q row of the lane's first step (2D: t = q, 3D: t), if next to the cut
+    const int tq = (DIM == 2) ? t + q : t;
+    L.og[q] = (L.t <= 1) ? glued_row(P, L.r0, tq, L.y[q]) * P.G + L.w : 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L.gm[q][i] = (i < W) ? glued_mask(P.l - q - 8 * (L.w + i)) : 0u;
   }
   return L;
 }
@@ -691,10 +705,11 @@ __device__ __forceinline__ void rows_pm(const JP& P, const LanePM& lp, uint32_t*
       const int wrap_m1 = (DIM == 3) ? wrap_m : 0;
       row_update<DIM, true, W, C, CUT>(P, lp.w, lp.wl, lp.wr, Lc, Lo, thr, C, g, j, pos, dpos, work, dI, lp.r0,
                                        t, lp.y[0], pC, pO, wrap_m - LyG, LyG - wrap_p, lp.ymo[0], lp.ypo[0], c0,
-                                       c3);
+                                       c3, lp.og[0], lp.gm[C]);
       row_update<DIM, true, W, C ^ 1, CUT>(P, lp.w, lp.wl, lp.wr, Lc, Lo, thr, C, g, j, pos, dpos, work, dI,
                                            lp.r0, t1, lp.y[1], pC + lp.d_rw, pO + lp.d_rw, wrap_m1 - LyG,
-                                           LyG - wrap_p1, lp.ymo[1], lp.ypo[1], c0 + lp.d_c0, c3);
+                                           LyG - wrap_p1, lp.ymo[1], lp.ypo[1], c0 + lp.d_c0, c3, lp.og[1],
+                                           lp.gm[C ^ 1]);
     };
     // Both rows of a step are next to the cut or neither is (t <= 1 implies
     // t1 <= 1 in 2D, t1 = t in 3D).  The code for rows next to the cut runs
@@ -798,7 +813,7 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
   LanePM lp;
   bool on = active;
   if constexpr (PM) {
-    lp = make_lane_pm<DIM>(P, lt_, T, W);
+    lp = make_lane_pm<DIM, W>(P, lt_, T);
   } else {
     ln = make_lane(P, lt_, T, W, true);
     on = active && ln.kstart < ln.kend;
