@@ -183,13 +183,13 @@ def test_launch_shapes_give_identical_bits(cfg):
 
 
 WIDE_SPECS = [
-    # lx/2 a multiple of 16: lanes of the wide kernel take four words (16 sites)
+    # lx/2 a multiple of 16: a lane takes four words (16 sites) of a row
     dict(dim=2, lt=16, lx=32, ly=1, n=2, beta=BC2, l=13, n_step=8, n_traj=6, seed=31),
     dict(dim=2, lt=8, lx=64, ly=1, n=3, beta=BC2, l=37, n_step=6, n_traj=5, seed=32, reverse=True),
     dict(dim=2, lt=4, lx=96, ly=1, n=2, beta=0.3, l=70, n_step=5, n_traj=3, seed=33, spin_format=1),
     dict(dim=3, lt=8, lx=32, ly=4, n=2, beta=BC3, l=22, n_step=8, n_traj=4, seed=34, subsets=True),
     dict(dim=2, lt=6, lx=32, ly=1, n=2, beta=BC2, l=31, n_step=4, n_traj=3, seed=35),
-    # rows of three words: one wide-kernel lane takes a whole row (12 sites)
+    # rows of three words: one lane takes a whole row (12 sites)
     dict(dim=2, lt=8, lx=24, ly=1, n=2, beta=BC2, l=17, n_step=6, n_traj=5, seed=36),
     dict(dim=3, lt=4, lx=24, ly=4, n=3, beta=BC3, l=10, n_step=8, n_traj=3, seed=37, subsets=True),
     dict(dim=3, lt=6, lx=24, ly=2, n=2, beta=0.25, l=23, n_step=4, n_traj=4, seed=38, spin_format=1, reverse=True),
