@@ -228,6 +228,48 @@ def test_launch_shapes_give_identical_bits(cfg):
         j.close()
 
 
+# The same jobs under launch shapes that take either row order of the
+# on-chip kernel: with T lanes per trajectory, S = T / (G / W) row slots and
+# B = S / n per replica, the parity-major order runs when B < R (and, in 3D,
+# ly divides B), the lane-map order otherwise.  The batch path packs as many
+# trajectories per workgroup as the LDS budget allows (ties to the larger
+# count); the per-job path keeps one per workgroup for jobs this small.
+ROW_ORDER_CASES = [
+    # 2D 16x64 (2 KiB per trajectory): G = 8, W = 4, R = 16.  One trajectory
+    # per 64 lanes: B = 16 = R (lane map); two: B = 8 (parity-major).
+    ("2d_lanemap", dict(dim=2, lt=16, lx=64, ly=1, n=2, beta=BC2, l=21, n_step=6, n_traj=4, seed=71),
+     dict(block_threads=64, lds_bytes=2048)),
+    ("2d_paritymajor", dict(dim=2, lt=16, lx=64, ly=1, n=2, beta=BC2, l=21, n_step=6, n_traj=4, seed=71),
+     dict(block_threads=64, lds_bytes=4096)),
+    # 3D 4x32x4 (1 KiB per trajectory): G = 4, W = 4, R = 16.  T = 64: B = 32
+    # (lane map); four trajectories per 64 lanes: B = 8, a multiple of ly
+    # (parity-major).
+    ("3d_lanemap", dict(dim=3, lt=4, lx=32, ly=4, n=2, beta=BC3, l=9, n_step=6, n_traj=4, seed=72),
+     dict(block_threads=64, lds_bytes=1024)),
+    ("3d_paritymajor", dict(dim=3, lt=4, lx=32, ly=4, n=2, beta=BC3, l=9, n_step=6, n_traj=4, seed=72),
+     dict(block_threads=64, lds_bytes=4096)),
+]
+
+
+@pytest.mark.parametrize("name,kw,cfg", ROW_ORDER_CASES, ids=[c[0] for c in ROW_ORDER_CASES])
+def test_both_row_orders_match_oracle(name, kw, cfg):
+    s = ee.JobSpec(**kw)
+    say(f"[gpu] row order {name}: {cfg}")
+    I_or, sp_or = eo.run(oracle_job(s), 3, want_spins=True)
+    j = ee.Job(s)
+    j.set_launch(cfg)
+    j.thermalize(3)
+    j.run_protocol()
+    assert np.array_equal(j.work(), I_or)
+    assert np.array_equal(j.spins(), sp_or)
+    j.close()
+    jobs = [ee.Job(s)]
+    ee.batch_run(jobs, 3, cfg=cfg)
+    assert np.array_equal(jobs[0].work(), I_or)
+    assert np.array_equal(jobs[0].spins(), sp_or)
+    jobs[0].close()
+
+
 @pytest.mark.parametrize("cfg", [dict(block_threads=64), dict(block_threads=128), dict()])
 def test_rows_wider_than_the_requested_block(cfg):
     # lx = 2048: 256 words per row; a 64-thread block is raised to 256 so
