@@ -207,9 +207,9 @@ WIDE_SPECS = [
                                  dict(block_threads=512),
                                  dict(block_threads=64, lds_bytes=1024),
                                  dict()])
-def test_launch_shapes_give_identical_bits(cfg):
+def test_multiword_lanes_give_identical_bits(cfg):
     specs = [ee.JobSpec(**kw) for kw in WIDE_SPECS]
-    say(f"[gpu] launch shape {cfg}")
+    say(f"[gpu] multi-word lanes, launch shape {cfg}")
     jobs = [ee.Job(s) for s in specs]
     ee.batch_run(jobs, 4, cfg=cfg)
     for s, j in zip(specs, jobs):
