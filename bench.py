@@ -24,10 +24,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 32-bit VALU lane-ops/s.
-PEAK_INT_LANE_OPS = 256 * 4 * 16 * 2.4e9
-PEAK_HBM_GBPS = 8000.0           # MI355X HBM3E
-STREAM_BYTES_PER_ATTEMPT = 1.5   # int8 planes streamed from HBM: opposite plane read, own plane read + written
+PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
+# Algorithmic HBM bytes of one Metropolis attempt: an int8 spin read and
+# written once per sweep.  The persistent kernel keeps every lattice in LDS
+# and moves far less (the measured traffic is reported beside it); the
+# figure is the per-attempt traffic of the method streamed at one byte per
+# spin, the basis on which the HBM roofline of the path is stated.
+BYTES_PER_ATTEMPT = 2.0
+# The HBM-streaming path as built: one launch per colour, each reading the
+# opposite plane and reading and writing its own plane, i.e. 3 bytes per
+# site per sweep.
+STREAM_BYTES_PER_ATTEMPT = 3.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_2d64_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_03311_amd", "csrc", f) for f in ("ee_kernels.hip", "ee_internal.hpp")]
 
@@ -40,33 +47,60 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def ops_per_attempt(dim: int) -> float:
-    """Algorithmic VALU lane-instructions per Metropolis attempt on gfx950.
-
-    The minimal instruction sequence of the method: an eighth of one
-    Philox4x32-10 call (10 rounds of 2 v_mad_u64_u32 and 2 three-input xor =
-    40 per call, eight 16-bit fields) = 5, plus, per 32-bit word of 4
-    same-colour sites: 2*dim xor-add of the anti-aligned neighbour counts,
-    1 byte-align for the x neighbours, 4 byte permutes that look the
-    thresholds up and pair them as 16-bit lanes, 1 xor that offsets the
-    fields not offset inside Philox, 2 packed saturating differences, 2
-    packed minima for the tie test, and 1 permute, 1 shift and 1 three-input
-    op that gather and apply the flips."""
-    return 5.0 + (2 * dim + 1 + 4 + 1 + 2 + 2 + 3) / 4.0
+def hbm_frac(attempts: float, seconds: float, bytes_per_attempt: float = BYTES_PER_ATTEMPT) -> float:
+    return bytes_per_attempt * attempts / seconds / 1e9 / PEAK_HBM_GBPS
 
 
-def cpu_baseline(n_traj_sample: int) -> dict:
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_range(args):
+    """One worker of the parallel CPU leg: trajectories [j0, j1) of a job."""
+    from oracle import oracle as eo
+    spec, n_therm, j0, j1 = args
+    job = eo.Job(*spec)
+    t0 = time.perf_counter()
+    eo.run(job, n_therm, j0, j1)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(n_traj_sample: int, procs: int | None = None) -> dict:
+    """The CPU oracle on the host: one process on trajectories 0..n-1 of the
+    l = 32 job of the 2D 64x64 set, then P processes (the host's usable
+    cores, at most 16) on n trajectories each, disjoint.  Runs before the GPU
+    is touched (the workers are forked)."""
+    import multiprocessing as mp
     from oracle import oracle as eo
     from paper_2304_03311_amd import workloads
     s = workloads.config2_jobs()[32]
-    job = eo.Job(s.dim, s.lt, s.lx, s.ly, s.n, s.beta, s.l, s.n_step, s.n_traj, s.seed)
+    spec = (s.dim, s.lt, s.lx, s.ly, s.n, s.beta, s.l, s.n_step, s.n_traj, s.seed)
+    per_traj = s.sites * (workloads.N_THERM + s.n_step)
     t0 = time.perf_counter()
-    eo.run(job, workloads.N_THERM, 0, n_traj_sample)
-    dt = time.perf_counter() - t0
-    att = n_traj_sample * s.sites * (workloads.N_THERM + s.n_step)
-    return {"value": att / (dt * 1e9), "unit": "attempts/ns", "cores": 1, "kind": "oracle",
-            "sample": f"job l=32 of the 2D 64x64 set, trajectories 0..{n_traj_sample - 1} "
-                      f"({att:.3g} attempts, {dt:.1f} s, single-threaded C oracle)"}
+    eo.run(eo.Job(*spec), workloads.N_THERM, 0, n_traj_sample)
+    dt1 = time.perf_counter() - t0
+    if procs is None:
+        procs = min(16, len(os.sched_getaffinity(0)))
+    ranges = [(spec, workloads.N_THERM, p * n_traj_sample, (p + 1) * n_traj_sample) for p in range(procs)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        pool.map(_oracle_range, ranges)
+    dtp = time.perf_counter() - t0
+    att1 = n_traj_sample * per_traj
+    attp = procs * n_traj_sample * per_traj
+    return {"value": attp / (dtp * 1e9), "unit": "attempts/ns", "cores": procs, "kind": "oracle",
+            "cpu_model": _cpu_model(),
+            "sample": f"job l=32 of the 2D 64x64 set: {procs} processes of the single-threaded C oracle, "
+                      f"{n_traj_sample} disjoint trajectories each ({attp:.3g} attempts, {dtp:.1f} s wall)",
+            "single_core": {"value": att1 / (dt1 * 1e9), "cores": 1,
+                            "sample": f"trajectories 0..{n_traj_sample - 1} ({att1:.3g} attempts, {dt1:.1f} s)"}}
 
 
 def serving_run(n_jobs: int, rate: float = 200.0) -> dict:
@@ -116,8 +150,8 @@ def _time_per_job(jobs, n_therm):
 
 
 def configs_run() -> dict:
-    """The other job sets, each through the persistent batched path (tuned
-    launch shape) and through the per-job launch path."""
+    """The other job sets, each through the persistent batched path (the
+    tuner's launch shape) and through the per-job launch path."""
     from paper_2304_03311_amd import autotune, ee, workloads
     n_therm = workloads.N_THERM
     sets = {"c1_2d_16x16": [workloads.config1_job()],
@@ -128,12 +162,11 @@ def configs_run() -> dict:
         launch = autotune.cached(specs, n_therm) or autotune.tune(specs, n_therm)
         jobs = [ee.Job(s) for s in specs]
         att = sum(s.n_traj * s.sites * (n_therm + s.n_step) for s in specs)
-        ops = sum(ops_per_attempt(s.dim) * s.n_traj * s.sites * (n_therm + s.n_step) for s in specs)
         dt, kms, res = _time_batch(jobs, n_therm, launch)
         dtp, _ = _time_per_job(jobs, n_therm)
         out[name] = {"jobs": len(specs), "attempts": att, "batched_ms": dt * 1e3,
                      "batched_attempts_per_ns": att / (dt * 1e9), "kernel_ms": kms,
-                     "alu_frac": ops / (kms * 1e-3) / PEAK_INT_LANE_OPS,
+                     "hbm_frac": hbm_frac(att, kms * 1e-3),
                      "jobs_per_s": len(specs) / dt, "per_job_path_ms": dtp * 1e3,
                      "per_job_path_attempts_per_ns": att / (dtp * 1e9),
                      "dS_first": res[0].dS, "dS_err_first": res[0].dF_err, "launch": launch}
@@ -163,7 +196,7 @@ def streaming_run() -> dict:
             "ms": dt * 1e3, "launches": 2 * 110 + 3,
             "algorithmic_bytes_per_attempt": STREAM_BYTES_PER_ATTEMPT,
             "hbm_GBps_algorithmic": STREAM_BYTES_PER_ATTEMPT * r.attempts / dt / 1e9,
-            "hbm_frac": STREAM_BYTES_PER_ATTEMPT * r.attempts / dt / 1e9 / PEAK_HBM_GBPS}
+            "hbm_frac": hbm_frac(r.attempts, dt, STREAM_BYTES_PER_ATTEMPT)}
 
 
 def main() -> int:
@@ -177,13 +210,13 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency) measurement")
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--tune", action="store_true",
-                    help="time the tuner's launch shape for the headline set instead of the fixed one")
+                    help="re-tune the headline set's launch shape instead of taking the shipped tuned one")
     ap.add_argument("--no-configs", action="store_true", help="skip the c1/c3/c4 job sets")
     ap.add_argument("--stream-only", action="store_true",
                     help="run only the HBM-streaming measurement (3D 96^3) and print its JSON (profiled runs)")
     ap.add_argument("--launch", default=None,
                     help='launch shape as JSON (ee_launch_cfg fields), e.g. \'{"block_threads": 256, '
-                         '"lds_bytes": 54272}\'; replaces the fixed shape')
+                         '"lds_bytes": 54272}\'; replaces the tuned shape')
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device-to-device once (HBM counter calibration)")
     args = ap.parse_args()
@@ -191,6 +224,9 @@ def main() -> int:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build runs on one GPU "
               f"(trajectories shard across GPUs by index; no multi-GPU path is built)", file=sys.stderr)
         return 2
+
+    # the CPU leg first: its worker processes are forked before the GPU is touched
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample)
 
     import numpy as np
     import torch
@@ -204,11 +240,11 @@ def main() -> int:
     specs = workloads.config2_jobs()
     stream = torch.cuda.current_stream()
     n_therm = workloads.N_THERM
-    launch = workloads.BENCH_LAUNCH
     if args.launch is not None:
         launch = json.loads(args.launch)
-    elif args.tune:
-        launch = autotune.cached(specs, n_therm) or autotune.tune(specs, n_therm, stream=stream)
+    else:
+        launch = (None if args.tune else autotune.cached(specs, n_therm)) or autotune.tune(specs, n_therm,
+                                                                                            stream=stream)
     jobs = [ee.Job(s, stream=stream) for s in specs]
     attempts_per_step = sum(s.n_traj * s.sites * (n_therm + s.n_step) for s in specs)
 
@@ -234,8 +270,7 @@ def main() -> int:
     ms_per_step = dt * 1e3 / args.steps
     value = attempts_per_step * args.steps / (dt * 1e9)
     k_avg_s = float(np.mean(kernel_ms)) * 1e-3
-    ops = ops_per_attempt(2) * attempts_per_step
-    achieved = ops / k_avg_s / 1e12
+    achieved = BYTES_PER_ATTEMPT * attempts_per_step / k_avg_s / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -262,19 +297,15 @@ def main() -> int:
                    "attempts_per_step": attempts_per_step, "parallelism": "1 GPU"},
         "jobs_per_s": len(specs) * args.steps / dt,
         "dS2_err_median": float(np.median([r.dF_err for r in res])),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_LANE_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / (PEAK_INT_LANE_OPS / 1e12), "traffic": traffic,
+        # HBM roofline of the dominant kernel on the algorithmic bytes (2 per
+        # attempt) of one launch; traffic = the bytes rocprofv3 counted per
+        # launch (FETCH_SIZE + WRITE_SIZE, calibrated), null when the kernel
+        # changed since they were taken.
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBPS, "traffic": traffic,
                      "kernel": "sweep_kernel (persistent)", "kernel_ms": k_avg_s * 1e3,
-                     "ops_per_attempt": ops_per_attempt(2),
+                     "bytes_per_attempt": BYTES_PER_ATTEMPT, "attempts_per_launch": attempts_per_step,
                      "attempts_per_ns_in_kernel": attempts_per_step / (k_avg_s * 1e9)},
-        # The persistent path keeps every lattice in LDS, so HBM does not bound
-        # it (traffic above).  For comparison, the roofline of a design that
-        # streams the int8 colour planes from HBM each half-sweep (read the
-        # opposite plane once, read and write the own plane: 1.5 B/attempt).
-        "hbm_streamed_equivalent": {
-            "bytes_per_attempt": STREAM_BYTES_PER_ATTEMPT,
-            "attempts_per_ns_at_peak": PEAK_HBM_GBPS / STREAM_BYTES_PER_ATTEMPT,
-            "frac": attempts_per_step / (k_avg_s * 1e9) / (PEAK_HBM_GBPS / STREAM_BYTES_PER_ATTEMPT)},
         "c2_fit_k": curve.get("fit_k"),
         "launch": launch,
     }
@@ -293,8 +324,8 @@ def main() -> int:
     if not args.no_serve:
         out["serving"] = serving_run(args.serve_jobs)
         out["streaming_path"] = streaming_run()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     for j in jobs:
         j.close()
     if args.calib_copy:

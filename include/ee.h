@@ -230,6 +230,11 @@ const char* ee_last_error(void);
 /* Library version string. */
 const char* ee_version(void);
 
+/* Hash of the sources the library was built from (the build script passes
+ * it in; the Python binding refuses a library whose hash differs from that
+ * of the sources next to it).  Never NULL. */
+const char* ee_build_id(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,18 +20,45 @@ import os
 
 from . import ee
 
-CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_launch.json")
+# The shipped cache holds the shapes tuned on an MI355X for the benchmark
+# job sets; EE_TUNE_CACHE points the tuner at another file.
+CACHE = os.environ.get("EE_TUNE_CACHE",
+                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_launch.json"))
+MAX_LDS = 160 * 1024 - 256
+
+
+def _cfg(block: int, lds: int) -> dict:
+    return {"block_threads": block, "lds_bytes": lds, "grid_blocks": 0, "use_graph": 1, "flags": 0}
+
 
 # block size x LDS budget per workgroup.  The small shapes (a wave or two,
 # an LDS budget of a few trajectories) spread latency-bound sets of small
 # lattices over more CUs.
 CANDIDATES = [
-    {"block_threads": b, "lds_bytes": lds, "grid_blocks": 0, "use_graph": 1, "flags": 0}
-    for blocks, ldss in (((256, 512, 1024), (40 * 1024, 53 * 1024, 80 * 1024, 160 * 1024 - 256)),
+    _cfg(b, lds)
+    for blocks, ldss in (((256, 512, 1024), (40 * 1024, 53 * 1024, 80 * 1024, MAX_LDS)),
                          ((64, 128), (1024, 2048, 4096)))
     for b in blocks
     for lds in ldss
 ]
+
+
+def traj_bytes(s: ee.JobSpec) -> int:
+    """LDS bytes of one trajectory (int8 colour planes, whole 32-bit words per row)."""
+    return 2 * s.n * s.lt * s.ly * ((s.lx // 2 + 3) // 4) * 4
+
+
+def candidates_for(specs: list[ee.JobSpec]) -> list[dict]:
+    """The static shapes plus one to four trajectories of the set's largest
+    lattice per workgroup of one or two waves (each wave then owns whole
+    trajectories, so its barriers wait for no other wave)."""
+    tb = max(traj_bytes(s) for s in specs)
+    extra = [_cfg(b, k * tb) for b in (64, 128) for k in (1, 2, 3, 4) if k * tb <= MAX_LDS]
+    out = []
+    for c in CANDIDATES + extra:
+        if c not in out:
+            out.append(c)
+    return out
 
 
 def signature(specs: list[ee.JobSpec], n_therm: int) -> str:
@@ -55,7 +82,7 @@ def tune(specs: list[ee.JobSpec], n_therm: int, trial_steps: int = 200, trial_th
          candidates=None, repeats: int = 3, stream=None, save: bool = True, verbose: bool = False) -> dict:
     """Pick the fastest launch shape for this job set; returns the ee_launch_cfg dict."""
     import torch
-    candidates = CANDIDATES if candidates is None else candidates
+    candidates = candidates_for(specs) if candidates is None else candidates
     # same lattice shapes and trajectory counts, shorter protocol
     trial_specs = [dataclasses.replace(s, n_step=min(s.n_step, trial_steps)) for s in specs]
     jobs = [ee.Job(s, stream=stream) for s in trial_specs]
@@ -78,6 +105,7 @@ def tune(specs: list[ee.JobSpec], n_therm: int, trial_steps: int = 200, trial_th
             j.close()
     results.sort(key=lambda x: x[0])
     best = dict(results[0][1])
+    best["trial_ms"] = results[0][0]
     if save:
         db = _load()
         db[signature(specs, n_therm)] = best

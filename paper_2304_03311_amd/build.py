@@ -1,6 +1,7 @@
 """Build the gfx950 shared library (HIP kernels + C ABI runtime) in-tree."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -18,20 +19,35 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-ff
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
 
 
+def source_hash() -> str:
+    """Hash of every source the library is built from (kernels, runtime,
+    internal headers and the public header)."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".hpp")))
+    for f in files + ["../../include/ee.h"]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tag = f"-DEE_SOURCE_HASH=\"{source_hash()}\""
+    # the sources compile in parallel (the kernel file takes minutes)
+    procs = []
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
-        lang = ["-x", "hip"]
-        cmd = [hipcc, *FLAGS[:-1], "-c", *lang, os.path.join(CSRC, src), "-o", obj]
-        cmd = [c for c in cmd if c != "-shared"]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
-        if verbose and r.stderr.strip():
-            print(r.stderr, file=sys.stderr)
+        cmd = [hipcc, *[f for f in FLAGS if f not in ("-shared", "-Wall")], "-Wall", tag, "-c", "-x", "hip",
+               os.path.join(CSRC, src), "-o", obj]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
         objs.append(obj)
+    for src, p in procs:
+        _, err = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{err}")
+        if verbose and err.strip():
+            print(err, file=sys.stderr)
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -11,7 +11,9 @@
 //                [m][fa][b][c]: fa = anti-aligned fixed
 //                neighbours (0..2dim-1), b = intra partner anti-aligned,
 //                c = inter partner anti-aligned
-//   [work]       n_traj x int64 integer works I_j
+//   [work]       n_traj x int64 integer works I_j, then 2 n_traj doubles of
+//                estimator scratch (the exponentials e_j and the
+//                leave-one-out estimates)
 //   [spins]      n_traj trajectories, each two colour planes
 //                [colour][replica][row = t*ly + y][word], where a row of one
 //                colour holds the lx/2 sites x = 2h + ((colour+t+y)&1),
@@ -35,6 +37,7 @@ constexpr int kMaxSlots = 16;  // trajectories per workgroup at most
 constexpr int kSweepTailBytes = 128;
 static_assert((4 + kMaxSlots + 8) * 4 <= kSweepTailBytes, "sweep LDS tables");
 inline int sweep_tail_words(int lds_bytes) { return (lds_bytes + 15) / 16 * 4; }
+constexpr int kEstimateThreads = 1024;  // workgroup size of the estimator kernel
 constexpr uint32_t kFlagInit = 1u;   // draw the initial spins (else load them)
 constexpr uint32_t kFlagProto = 2u;  // run the N protocol sweeps after n_therm sweeps
 

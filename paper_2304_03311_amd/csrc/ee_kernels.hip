@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 #include <type_traits>
 
+#include "ee_dd.hpp"
 #include "ee_internal.hpp"
 
 namespace {
@@ -205,8 +206,6 @@ __device__ __forceinline__ Lane make_lane(const JP& P, int lt_, int T, int W, bo
   }
   return ln;
 }
-
-__device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) { return (a ^ b) + c; }
 
 // (a ^ b) + c as one v_xad_u32.  Written out because the compiler splits a
 // chain of them into separate xors and three-input adds (six instructions
@@ -1074,50 +1073,43 @@ __global__ void queue_reset_kernel(int* queue) {
 }
 
 // ---------------------------------------------------------------------------
-// Estimator
+// Estimator (App. A, Jarzynski's equality), one workgroup per job.
+//
+// Every floating-point result is formed by the same operations in the same
+// order as the plain definition: the n_t exponentials e_j are summed one
+// after the other in ascending j, each leave-one-out sum is its own
+// ascending sum over j != i, and the mean and variance of W are sums of the
+// terms -(beta/S) I_j in ascending j.  exp and log are the correctly
+// rounded ones of ee_dd.hpp.  The order costs no time worth counting: the
+// long sums are a few thousand dependent FP64 adds, each done by one lane
+// while other waves do the others, and the leave-one-out sums run one per
+// lane (n_t^2 adds in all, e_j broadcast from LDS tiles).
 // ---------------------------------------------------------------------------
-constexpr int kEstThreads = 256;
-
+#pragma clang fp contract(off)
+constexpr int kEstThreads = ee::kEstimateThreads;
 constexpr int kEstWaves = kEstThreads / 64;
+constexpr int kEstTile = 4096;  // e_j per LDS tile (32 KiB)
+constexpr int kEstAcc = 8;      // leave-one-out sums per lane and pass
 
-// Reduction over the block: butterfly shuffles within each 64-lane wave,
-// then the kEstWaves wave results through LDS (sh: kEstWaves entries).
-template <typename T, typename Op>
-__device__ T block_reduce(T v, T* sh, Op op) {
+// Integer reduction over the block: butterfly shuffles within each 64-lane
+// wave, then the wave results through LDS (sh: kEstWaves entries).
+template <typename Op>
+__device__ long long block_reduce_ll(long long v, long long* sh, Op op) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  T r = sh[0];
+  long long r = sh[0];
 #pragma unroll
   for (int k = 1; k < kEstWaves; ++k) r = op(r, sh[k]);
   __syncthreads();
   return r;
 }
 
-// Exclusive prefix sum over the block in thread order: shuffle scan within
-// each wave, wave totals through LDS (sh: kEstWaves entries).
-__device__ double block_exclusive_scan(double v, double* sh) {
-  const int ln = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double incl = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const double u = __shfl_up(incl, off, 64);
-    if (ln >= off) incl += u;
-  }
-  if (ln == 63) sh[wv] = incl;
-  const double excl_wave = __shfl_up(incl, 1, 64);
-  __syncthreads();
-  double base = 0.0;
-  for (int k = 0; k < wv; ++k) base += sh[k];
-  __syncthreads();
-  return (ln == 0) ? base : base + excl_wave;
-}
-
 __global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* const* jobtab) {
-  __shared__ double shd[kEstWaves];
+  __shared__ double tile[kEstTile];
   __shared__ long long shl[kEstWaves];
-  __shared__ double csh[kEstThreads];
+  __shared__ double shd[4];
   const JobDev* J = jobtab[blockIdx.x];
   const int tid = threadIdx.x;
   const int n = J->n_traj;
@@ -1125,77 +1117,102 @@ __global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* con
   const double beta = J->beta;
   const double N = (double)J->S;  // W_j = -(beta/S) I_j
   ee_result* res = J->result;
-  double* scratch = reinterpret_cast<double*>(J->work + n);  // n doubles after the works
+  double* e = reinterpret_cast<double*>(J->work + n);  // n doubles: e_j
+  double* loo = e + n;                                 // n doubles: leave-one-out estimates
 
-  long long mx = LLONG_MIN, mn = LLONG_MAX, sm = 0;
+  long long mx = LLONG_MIN, mn = LLONG_MAX;
   for (int i = tid; i < n; i += kEstThreads) {
     const long long v = I[i];
     mx = v > mx ? v : mx;
     mn = v < mn ? v : mn;
-    sm += v;
   }
-  const long long imax = block_reduce(mx, shl, [](long long a, long long b) { return a > b ? a : b; });
-  const long long imin = block_reduce(mn, shl, [](long long a, long long b) { return a < b ? a : b; });
-  const long long isum = block_reduce(sm, shl, [](long long a, long long b) { return a + b; });
+  const long long imax = block_reduce_ll(mx, shl, [](long long a, long long b) { return a > b ? a : b; });
+  const long long imin = block_reduce_ll(mn, shl, [](long long a, long long b) { return a < b ? a : b; });
+  for (int i = tid; i < n; i += kEstThreads) e[i] = ee::dd::exp_cr((beta * (double)(I[i] - imax)) / N);
+  __syncthreads();
 
-  // contiguous chunks: thread t owns [t*C, min(n, (t+1)*C))
-  const int C = (n + kEstThreads - 1) / kEstThreads;
-  const int lo = min(n, tid * C), hi = min(n, lo + C);
-  double cs = 0.0, cs2 = 0.0;
-  for (int i = lo; i < hi; ++i) {
-    const double e = exp((beta * (double)(I[i] - imax)) / N);
-    scratch[i] = cs;  // prefix within the chunk
-    cs += e;
-    cs2 += e * e;
-  }
-  const double s = block_reduce(cs, shd, [](double a, double b) { return a + b; });
-  const double s2 = block_reduce(cs2, shd, [](double a, double b) { return a + b; });
-  // sums of the chunks before (pre) and after (suf) this thread's, each by
-  // its own scan so that the leave-one-out sums are formed without
-  // subtracting from the total (no cancellation)
-  const double pre = block_exclusive_scan(cs, shd);
-  csh[tid] = cs;
-  __syncthreads();
-  const double suf = block_exclusive_scan(csh[kEstThreads - 1 - tid], shd);  // over chunks > this one, reversed
-  __syncthreads();
-  csh[kEstThreads - 1 - tid] = suf;
-  __syncthreads();
-  const double after0 = csh[tid];
-  const double shift = (beta * (double)imax) / N;
-  const double dF = -(shift + log(s) - log((double)n));
-  double loo_sum = 0.0;
-  if (n >= 2) {
-    double after = after0;  // sum over later chunks
-    for (int i = hi - 1; i >= lo; --i) {
-      const double e = exp((beta * (double)(I[i] - imax)) / N);
-      const double si = (pre + scratch[i]) + after;  // sum over j != i
-      after += e;
-      const double loo = -(shift + log(si) - log((double)(n - 1)));
-      scratch[i] = loo;
-      loo_sum += loo;
-    }
-  }
-  const double loo_mean = block_reduce(loo_sum, shd, [](double a, double b) { return a + b; }) / n;
-  const double wscale = beta / N;
-  const double wmean = -wscale * ((double)isum / (double)n);
-  double dev = 0.0, wdev = 0.0;
-  for (int i = lo; i < hi; ++i) {
-    if (n >= 2) {
-      const double d = scratch[i] - loo_mean;
-      dev += d * d;
-    }
-    const double wd = -wscale * (double)I[i] - wmean;
-    wdev += wd * wd;
-  }
-  const double dev_sum = block_reduce(dev, shd, [](double a, double b) { return a + b; });
-  const double wvar = block_reduce(wdev, shd, [](double a, double b) { return a + b; }) / n;
+  // The sums in ascending j, each by one lane of its own wave.
   if (tid == 0) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += e[j];
+    shd[0] = s;
+  } else if (tid == 64) {
+    double s2 = 0.0;
+    for (int j = 0; j < n; ++j) s2 += e[j] * e[j];
+    shd[1] = s2;
+  } else if (tid == 128) {
+    double wm = 0.0;
+    for (int j = 0; j < n; ++j) wm += -(beta / N) * (double)I[j];
+    wm /= n;
+    double wv = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double d = -(beta / N) * (double)I[j] - wm;
+      wv += d * d;
+    }
+    wv /= n;
+    shd[2] = wm;
+    shd[3] = wv;
+  }
+  __syncthreads();
+  const double s = shd[0];
+  const double shift = (beta * (double)imax) / N;
+  const double dF = -(shift + ee::dd::log_cr(s) - ee::dd::log_cr((double)n));
+
+  if (n >= 2) {
+    // leave-one-out sums S_i = sum_{j != i} e_j, ascending j: lane t takes
+    // i = t, t + T, ... in passes of A sums; adding +0.0 for j = i leaves a
+    // sum of non-negative terms unchanged, so it stands for skipping j.
+    const double log_n1 = ee::dd::log_cr((double)(n - 1));
+    const int per_lane = (n + kEstThreads - 1) / kEstThreads;
+    const auto passes = [&](auto acount) {
+      constexpr int A = decltype(acount)::value;
+      for (int p0 = 0; p0 < per_lane; p0 += A) {
+        double acc[A];
+        int idx[A];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+          acc[a] = 0.0;
+          idx[a] = tid + (p0 + a) * kEstThreads;
+        }
+        for (int t0 = 0; t0 < n; t0 += kEstTile) {
+          const int len = min(kEstTile, n - t0);
+          __syncthreads();
+          for (int q = tid; q < len; q += kEstThreads) tile[q] = e[t0 + q];
+          __syncthreads();
+          for (int q = 0; q < len; ++q) {
+            const double v = tile[q];
+            const int j = t0 + q;
+#pragma unroll
+            for (int a = 0; a < A; ++a) acc[a] += (j == idx[a]) ? 0.0 : v;
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+          if (idx[a] < n) loo[idx[a]] = -(shift + ee::dd::log_cr(acc[a]) - log_n1);
+      }
+    };
+    if (per_lane <= 1) passes(std::integral_constant<int, 1>{});
+    else if (per_lane <= 2) passes(std::integral_constant<int, 2>{});
+    else if (per_lane <= 4) passes(std::integral_constant<int, 4>{});
+    else passes(std::integral_constant<int, kEstAcc>{});
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double err = __builtin_nan("");
+    if (n >= 2) {
+      double mean = 0.0;
+      for (int i = 0; i < n; ++i) mean += loo[i];
+      mean /= n;
+      double acc = 0.0;
+      for (int i = 0; i < n; ++i) acc += (loo[i] - mean) * (loo[i] - mean);
+      err = sqrt((double)(n - 1) / (double)n * acc);
+    }
     res->dF = dF;
     res->dS = dF / (double)(J->n - 1);
-    res->dF_err = (n >= 2) ? sqrt((double)(n - 1) / (double)n * dev_sum) : __builtin_nan("");
-    res->w_mean = wmean;
-    res->w_var = wvar;
-    res->ess = s * s / s2;
+    res->dF_err = err;
+    res->w_mean = shd[2];
+    res->w_var = shd[3];
+    res->ess = s * s / shd[1];
     res->i_min = imin;
     res->i_max = imax;
     res->n_traj = n;

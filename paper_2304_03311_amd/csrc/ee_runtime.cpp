@@ -93,9 +93,11 @@ ee_status validate(const ee_job_desc* d) {
     return fail(EE_EINVAL, "unknown flags 0x%x", d->flags);
   if ((d->flags & EE_FLAG_SUBSETS) && d->n_step % d->ly)
     return fail(EE_EINVAL, "the subset protocol needs n_step divisible by ly (%d %% %d)", d->n_step, d->ly);
-  // |I| <= 2 n ly N must fit the int32 accumulators
-  if (2.0 * d->n_replicas * d->ly * (double)d->n_step >= 2147483647.0)
-    return fail(EE_EINVAL, "2*n*ly*n_step exceeds the int32 work range");
+  // |I| <= 2 n ly N (2 n ly l N with the whole-region protocol, which ramps
+  // the l columns x < l) must fit the int32 accumulators
+  const double ramped_cols = (d->flags & EE_FLAG_WHOLE) ? (double)d->l : 1.0;
+  if (2.0 * d->n_replicas * d->ly * ramped_cols * (double)d->n_step >= 2147483647.0)
+    return fail(EE_EINVAL, "the work bound 2*n*ly*(ramped columns)*n_step exceeds the int32 range");
   if ((double)d->lt * d->ly * d->lx > 1e8) return fail(EE_EINVAL, "lattice too large");
   return EE_OK;
 }
@@ -114,7 +116,7 @@ Layout layout_of(const ee_job_desc* d) {
   L.off_selfptr = off; off = align_up(off + sizeof(void*));
   L.off_result = off; off = align_up(off + sizeof(ee_result));
   L.off_ramp = off; off = align_up(off + (size_t)(d->n_step + 1) * 8 * d->dim * sizeof(uint32_t));
-  L.off_work = off; off = align_up(off + 2 * (size_t)d->n_traj * sizeof(int64_t));  // I_j + estimator scratch
+  L.off_work = off; off = align_up(off + 3 * (size_t)d->n_traj * sizeof(int64_t));  // I_j + estimator scratch
   L.off_spins = off; off = align_up(off + (size_t)d->n_traj * L.storage_words_per_traj * 4);
   L.total = off;
   return L;
@@ -454,7 +456,7 @@ ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launc
     void* a_est[] = {&jt};
     kp.func = const_cast<void*>(f_est);
     kp.gridDim = dim3(count);
-    kp.blockDim = dim3(256);
+    kp.blockDim = dim3(ee::kEstimateThreads);
     kp.sharedMemBytes = 0;
     kp.kernelParams = a_est;
     if (e == hipSuccess) e = hipGraphAddKernelNode(&n_est, g, &n_ev1, 1, &kp);
@@ -488,7 +490,12 @@ ee_status run_plan(Plan* P, hipStream_t stream) {
 extern "C" {
 
 const char* ee_last_error(void) { return g_err.c_str(); }
-const char* ee_version(void) { return "ee-mi355x 0.1 (gfx950)"; }
+const char* ee_version(void) { return "ee-mi355x 0.2 (gfx950)"; }
+
+#ifndef EE_SOURCE_HASH
+#define EE_SOURCE_HASH "unknown"
+#endif
+const char* ee_build_id(void) { return EE_SOURCE_HASH; }
 
 ee_status ee_job_footprint(const ee_job_desc* desc, size_t* bytes) {
   g_err.clear();

@@ -69,7 +69,7 @@ _SIGS = {
     "ee_batch_kernel_ms": [ctypes.POINTER(ctypes.c_double)],
     "ee_job_destroy": [ctypes.c_void_p],
 }
-EXPORTED = list(_SIGS) + ["ee_last_error", "ee_version"]
+EXPORTED = list(_SIGS) + ["ee_last_error", "ee_version", "ee_build_id"]
 
 
 def lib() -> ctypes.CDLL:
@@ -87,6 +87,13 @@ def lib() -> ctypes.CDLL:
         L.ee_last_error.argtypes = []
         L.ee_version.restype = ctypes.c_char_p
         L.ee_version.argtypes = []
+        L.ee_build_id.restype = ctypes.c_char_p
+        L.ee_build_id.argtypes = []
+        from .build import source_hash
+        built, here = L.ee_build_id().decode(), source_hash()
+        if built != here:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (build id {built}, sources {here}); "
+                               f"run __graft_entry__.build() again")
         _lib = L
     return _lib
 

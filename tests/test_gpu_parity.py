@@ -1,7 +1,8 @@
 """GPU parity of the HIP path with the CPU oracle, through the C ABI.
 
-Bar: spins and integer works bit-exact; Delta F and the other FP64 outputs
-within the tolerance derived from the estimator's arithmetic (see DF_TOL).
+Bar: spins and integer works bit-exact; Delta F within
+1e-12 max(|Delta F|, 1e-3), the mean and variance of W equal, the jackknife
+error and the ESS within 1e-12 relative (see check_estimate).
 """
 from __future__ import annotations
 
@@ -34,12 +35,9 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def df_tol(est: eo.Estimate, beta: float, N: int, n_t: int) -> float:
-    """Delta F = -(beta I_max/N + log s - log n_t) is a sum of terms of size
-    |beta I_max / N| and log n_t; the sum s of n_t exponentials is accurate to
-    ~n_t ulp on either side.  1e-12 relative to that scale."""
-    scale = max(1.0, abs(beta * est.i_max / N) + math.log(max(n_t, 2)))
-    return 1e-12 * scale
+# Largest |dF_gpu - dF_oracle| / max(|dF_oracle|, 1e-3) seen in this session,
+# printed by the last test of the module.
+_DF_WORST = [0.0, ""]
 
 
 def oracle_job(s: ee.JobSpec) -> eo.Job:
@@ -47,18 +45,32 @@ def oracle_job(s: ee.JobSpec) -> eo.Job:
                   s.whole)
 
 
-def check_estimate(res: ee.ee_result, I: np.ndarray, s: ee.JobSpec):
+def check_estimate(res: ee.ee_result, I: np.ndarray, s: ee.JobSpec, label: str = ""):
+    """The GPU estimate against the oracle's on the same integer works.
+
+    The kernel forms every FP64 output by the oracle's operations in the
+    oracle's order, with correctly rounded exp and log, so the two differ
+    only where the host's libm rounds exp or log the other way (about one
+    evaluation in a thousand, each by one ulp).  Delta F: within
+    1e-12 max(|Delta F|, 1e-3) (1e-12 relative; the floor keeps the bound
+    meaningful where Delta F crosses zero).  The mean and variance of W are
+    sums of correctly rounded products in the same order: equal.  The
+    jackknife error and the ESS: 1e-12 relative."""
     est = eo.estimate(I, s.beta, s.S, s.n)
-    tol = df_tol(est, s.beta, s.S, s.n_traj)
-    assert abs(res.dF - est.dF) <= tol, (res.dF, est.dF, tol)
-    assert abs(res.dS - est.dS) <= tol
+    floor = max(abs(est.dF), 1e-3)
+    rel = abs(res.dF - est.dF) / floor
+    say(f"[gpu]   {label} dF gpu {res.dF!r} oracle {est.dF!r} |diff|/max(|dF|,1e-3) = {rel:.3g}")
+    if rel > _DF_WORST[0]:
+        _DF_WORST[:] = [rel, label]
+    assert abs(res.dF - est.dF) <= 1e-12 * floor, (res.dF, est.dF)
+    assert abs(res.dS - est.dS) <= 1e-12 * max(abs(est.dS), 1e-3)
     assert res.i_min == est.i_min and res.i_max == est.i_max
     if s.n_traj >= 2:
-        assert res.dF_err == pytest.approx(est.dF_err, rel=1e-9, abs=1e-13)
+        assert res.dF_err == pytest.approx(est.dF_err, rel=1e-12, abs=1e-300)
     else:
         assert math.isnan(res.dF_err) and math.isnan(est.dF_err)
-    assert res.w_mean == pytest.approx(est.w_mean, rel=1e-12, abs=1e-14)
-    assert res.w_var == pytest.approx(est.w_var, rel=1e-9, abs=1e-14)
+    assert res.w_mean == est.w_mean
+    assert res.w_var == est.w_var
     assert res.ess == pytest.approx(est.ess, rel=1e-12)
 
 
@@ -115,7 +127,7 @@ def test_per_job_path_matches_oracle(name, kw, n_therm):
     I_or, sp_or = eo.run(oracle_job(s), n_therm, want_spins=True)
     assert np.array_equal(I_gpu, I_or)
     assert np.array_equal(sp_gpu, sp_or)
-    check_estimate(res, I_or, s)
+    check_estimate(res, I_or, s, name)
     assert res.attempts == s.n_traj * s.sites * (n_therm + s.n_step)
     job.close()
 
@@ -145,7 +157,7 @@ def test_batch_path_matches_per_job_and_oracle():
         I_or, sp_or = eo.run(oracle_job(s), n_therm, want_spins=True)
         assert np.array_equal(job.work(), I_or), s
         assert np.array_equal(job.spins(), sp_or), s
-        check_estimate(job.estimate(), I_or, s)
+        check_estimate(job.estimate(), I_or, s, f"batch l={s.l}")
     # replay of the recorded graph: identical results
     first = [j.work() for j in jobs]
     for j in jobs:
@@ -376,17 +388,25 @@ def test_state_machine_errors():
     job.close()
 
 
+def _bench_launch(specs):
+    """The launch shape bench.py times for a job set: the tuner's cached
+    choice, else a fresh tuning."""
+    from paper_2304_03311_amd import autotune
+    return autotune.cached(specs, workloads.N_THERM) or autotune.tune(specs, workloads.N_THERM)
+
+
 def test_full_size_2d_64x64_batch_sampled():
     """The 2D 64x64 workload (64 jobs, l = 0..63, N = 1000, n_t = 1024) in the
     benchmark's launch configuration; sampled trajectories vs the oracle and
     whole-batch invariants."""
     specs = workloads.config2_jobs()
     n_therm = workloads.N_THERM
-    say(f"[gpu] full 64x64 batch: {len(specs)} jobs x {specs[0].n_traj} trajectories")
+    launch = _bench_launch(specs)
+    say(f"[gpu] full 64x64 batch: {len(specs)} jobs x {specs[0].n_traj} trajectories, launch {launch}")
     jobs = [ee.Job(s) for s in specs]
-    ee.batch_run(jobs, n_therm, cfg=workloads.BENCH_LAUNCH)
+    ee.batch_run(jobs, n_therm, cfg=launch)
     rng = np.random.default_rng(7)
-    for ji, j in [(0, 0), (17, 1023), (40, int(rng.integers(0, 1024))), (63, 511)]:
+    for ji, j in [(0, 0), (17, 1023), (40, int(rng.integers(0, 1024))), (63, 511), (31, 300), (32, 777)]:
         s = specs[ji]
         I_or, sp_or = eo.run(oracle_job(s), n_therm, j, j + 1, want_spins=True)
         say(f"[gpu]   sample job l={s.l} j={j}")
@@ -396,25 +416,57 @@ def test_full_size_2d_64x64_batch_sampled():
         I = job.work()
         assert np.all(np.abs(I) <= 2 * s.n * s.ly * s.n_step)
         assert np.all(I % 2 == 0)
-        check_estimate(job.estimate(), I, s)  # the estimator at n_t = 1024 vs the oracle's
+        check_estimate(job.estimate(), I, s, f"64x64 l={s.l}")  # the estimator at n_t = 1024
     for j in jobs:
         j.close()
 
 
 def test_full_size_3d_32cube_sampled():
+    """The 3D 32^3 bit-packed job through the per-job path and through the
+    batched launch shape the benchmark times."""
     s = workloads.config3_job()
     say(f"[gpu] full 32^3 job: {s}")
     job = ee.Job(s)
     job.thermalize(workloads.N_THERM)
     job.run_protocol()
-    j = 257
-    I_or, sp_or = eo.run(oracle_job(s), workloads.N_THERM, j, j + 1, want_spins=True)
-    assert job.work()[j] == I_or[0]
-    assert np.array_equal(job.spins(j + 1)[j], sp_or[0])
+    launch = _bench_launch([s])
+    say(f"[gpu]   batched with launch {launch}")
+    bjob = ee.Job(s)
+    ee.batch_run([bjob], workloads.N_THERM, cfg=launch)
+    for j in (257, 3, 511):
+        I_or, sp_or = eo.run(oracle_job(s), workloads.N_THERM, j, j + 1, want_spins=True)
+        say(f"[gpu]   sample j={j}")
+        for jb in (job, bjob):
+            assert jb.work()[j] == I_or[0]
+            assert np.array_equal(jb.spins(j + 1)[j], sp_or[0])
     I = job.work()
+    assert np.array_equal(I, bjob.work())
     assert np.all(np.abs(I) <= 2 * s.n * s.ly * s.n_step)
-    check_estimate(job.estimate(), I, s)
+    check_estimate(job.estimate(), I, s, "32^3")
+    check_estimate(bjob.estimate(), I, s, "32^3 batched")
     job.close()
+    bjob.close()
+
+
+def test_full_size_24_uneven_jobs_sampled():
+    """The 24 uneven jobs (2D L = 24..96, 3D L = 16..32, N = 500..2000) in one
+    persistent launch of the benchmark's shape: one sampled trajectory of
+    every job against the oracle, and every estimate."""
+    specs = workloads.config4_jobs()
+    launch = _bench_launch(specs)
+    say(f"[gpu] 24 uneven jobs, launch {launch}")
+    jobs = [ee.Job(s) for s in specs]
+    ee.batch_run(jobs, workloads.N_THERM, cfg=launch)
+    rng = np.random.default_rng(24)
+    for s, job in zip(specs, jobs):
+        j = int(rng.integers(0, s.n_traj))
+        say(f"[gpu]   sample D={s.dim} L={s.lx} N={s.n_step} l={s.l} j={j}")
+        I_or, sp_or = eo.run(oracle_job(s), workloads.N_THERM, j, j + 1, want_spins=True)
+        assert job.work()[j] == I_or[0]
+        assert np.array_equal(job.spins(j + 1)[j], sp_or[0])
+        check_estimate(job.estimate(), job.work(), s, f"c4 D={s.dim} L={s.lx} N={s.n_step}")
+    for j in jobs:
+        j.close()
 
 
 STREAM_CASES = [c for c in CASES if c[1].get("spin_format", 0) == 0 and c[1]["n_traj"] <= 16]
@@ -434,7 +486,7 @@ def test_streaming_path_matches_oracle(name, kw, n_therm):
     I_or, sp_or = eo.run(oracle_job(s), n_therm, want_spins=True)
     assert np.array_equal(job.work(), I_or)
     assert np.array_equal(job.spins(), sp_or)
-    check_estimate(job.estimate(), I_or, s)
+    check_estimate(job.estimate(), I_or, s, f"streaming {name}")
     job.close()
 
 
@@ -470,9 +522,15 @@ def test_lattices_beyond_lds_stream_from_hbm(kw):
     I_or, sp_or = eo.run(oracle_job(s), 4, want_spins=True)
     assert np.array_equal(job.work(), I_or)
     assert np.array_equal(job.spins(), sp_or)
-    check_estimate(job.estimate(), I_or, s)
+    check_estimate(job.estimate(), I_or, s, "large lattice")
     with pytest.raises(ee.EEError) as e:
         j2 = ee.Job(s)
         ee.batch_run([j2], 1)
     assert e.value.status == ee.EE_EUNSUPPORTED
     job.close()
+
+
+def test_zz_estimator_worst_case_report():
+    """Prints the largest Delta F deviation of the module's parity checks."""
+    say(f"[gpu] largest |dF_gpu - dF_oracle| / max(|dF_oracle|, 1e-3) = {_DF_WORST[0]:.3g} ({_DF_WORST[1]})")
+    assert _DF_WORST[0] <= 1e-12

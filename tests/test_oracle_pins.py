@@ -379,6 +379,90 @@ def test_estimator_bounds_and_closed_forms():
     assert math.isnan(eo.estimate(np.array([5]), beta, N, 2).dF_err)
 
 
+def _decimal_estimate(I, beta, N, n_rep):
+    """The estimator's outputs from their definitions (App. A: Delta F =
+    -log <exp(-W)> over the n_t trajectories, W_j = -(beta/N) I_j; the
+    delete-one jackknife; the mean and population variance of W; the
+    effective sample size (sum e)^2 / sum e^2 with e_j = exp(-W_j)),
+    evaluated in 50-digit decimal arithmetic with no shift or reordering."""
+    getcontext().prec = 50
+    n = len(I)
+    b, NN = Decimal(beta), Decimal(N)
+    W = [-(b / NN) * Decimal(int(v)) for v in I]
+    e = [(-w).exp() for w in W]
+    se = sum(e)
+    dF = -(se / n).ln()
+    wm = sum(W) / n
+    wv = sum((w - wm) ** 2 for w in W) / n
+    ess = se * se / sum(x * x for x in e)
+    err = None
+    if n >= 2:
+        loo = [-((se - e[i]) / (n - 1)).ln() for i in range(n)]
+        lm = sum(loo) / n
+        err = (Decimal(n - 1) / n * sum((v - lm) ** 2 for v in loo)).sqrt()
+    return dF, dF / (n_rep - 1), err, wm, wv, ess
+
+
+ESTIMATOR_CASES = [(5, 0.44, 50, 2, 1), (37, 0.2216546, 2000, 3, 2), (300, 0.7, 256, 2, 3), (1024, BC2, 1000, 2, 4)]
+
+
+@pytest.mark.parametrize("n,beta,N,n_rep,seed", ESTIMATOR_CASES)
+def test_estimator_matches_decimal_definitions(n, beta, N, n_rep, seed):
+    """Every output of eo_estimate against its definition in 50-digit decimal
+    arithmetic: dF, dS, the jackknife error, the mean and population variance
+    of W and the ESS.  The tolerances are the oracle's FP64 rounding (dF and
+    the leave-one-out values are sums of terms of size log n_t); a sample
+    instead of population variance, a missing square or a dropped term
+    misses them by orders of magnitude."""
+    rng = np.random.default_rng(seed)
+    I = 2 * rng.integers(-3 * N // 4, 3 * N // 4, size=n) // max(1, N // 100)
+    est = eo.estimate(I, beta, N, n_rep)
+    dF, dS, err, wm, wv, ess = _decimal_estimate(I, beta, N, n_rep)
+    scale = abs(beta * float(I.max()) / N) + math.log(n)
+    assert abs(est.dF - float(dF)) <= 4e-16 * max(scale, 1.0) * math.sqrt(n)
+    assert abs(est.dS - float(dS)) <= 4e-16 * max(scale, 1.0) * math.sqrt(n)
+    assert est.w_mean == pytest.approx(float(wm), rel=1e-13, abs=1e-17)
+    assert est.w_var == pytest.approx(float(wv), rel=1e-12)
+    assert est.ess == pytest.approx(float(ess), rel=1e-13)
+    # the leave-one-out values differ from their mean by ~dF_err/n_t, so their
+    # FP64 rounding (~1e-16 of log n_t) is amplified by ~n_t log n_t / dF_err
+    assert est.dF_err == pytest.approx(float(err), rel=2e-15 * n * math.log(n) / float(err) + 1e-12)
+
+
+ESTIMATOR_MUTATIONS = {
+    "sample variance": ("wv /= n_t;", "wv /= (n_t - 1);"),
+    "variance without square": ("wv += d * d;", "wv += d * fabs(d);"),
+    "jackknife factor": ("err = sqrt((double)(n_t - 1) / (double)n_t * acc);", "err = sqrt(acc / (double)n_t);"),
+    "ess without square": ("out[5] = s * s / s2;", "out[5] = s / s2;"),
+    "log n_t dropped": ("double dF = -(shift + log(s) - log((double)n_t));", "double dF = -(shift + log(s));"),
+}
+
+
+def test_planted_estimator_mistakes_are_caught(tmp_path):
+    """Each plausible mistake in eo_estimate fails the decimal pin."""
+    src = open(os.path.join(os.path.dirname(obuild.ORACLE_SO), "ee_oracle.c")).read()
+    rng = np.random.default_rng(11)
+    I = 2 * rng.integers(-40, 40, size=23)
+    beta, N = 0.44, 50
+    dF, dS, err, wm, wv, ess = (float(v) for v in _decimal_estimate(I, beta, N, 2))
+    for name, (old, new) in ESTIMATOR_MUTATIONS.items():
+        assert src.count(old) == 1, name
+        path = tmp_path / (name.replace(" ", "_") + ".c")
+        path.write_text(src.replace(old, new))
+        so = str(path) + ".so"
+        subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-ffp-contract=off", str(path), "-o", so, "-lm"],
+                       check=True)
+        L = ctypes.CDLL(so)
+        L.eo_estimate.argtypes = eo.lib().eo_estimate.argtypes
+        L.eo_estimate.restype = ctypes.c_int
+        out = np.zeros(8)
+        Ic = np.ascontiguousarray(I, dtype=np.int64)
+        assert L.eo_estimate(Ic.ctypes.data, len(I), beta, N, 2, out.ctypes.data, None) == 0
+        got = dict(dF=out[0], err=out[2], wv=out[4], ess=out[5])
+        want = dict(dF=dF, err=err, wv=wv, ess=ess)
+        assert any(abs(got[k] - want[k]) > 1e-9 * max(abs(want[k]), 1e-3) for k in got), name
+
+
 # --------------------------------------------------------------------------
 # Planted mistakes
 # --------------------------------------------------------------------------
