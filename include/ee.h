@@ -213,6 +213,23 @@ typedef struct {
 ee_status ee_batch_run_cfg(ee_job* const* jobs, int32_t count, int32_t n_therm,
                            const ee_launch_cfg* cfg, void* hip_stream);
 
+/* Allocation-free variant of ee_batch_run_cfg, for callers that cannot
+ * allocate device memory (code that must not call hipMalloc: under graph
+ * capture, in tight serving loops, in harnesses that forbid it).  Same
+ * kernels and bit-identical results.  The queue counter, job table and
+ * unit table go into a fixed static device array of 2 MiB per GPU, held
+ * until the process ends; a batch whose tables need more (256 + 8 count
+ * rounded up to 256, plus 16 bytes per work unit) returns EE_EINVAL before
+ * any device work.  It calls no hipMalloc or hipFree, records no graph and
+ * creates no event (cfg->use_graph is ignored; ee_batch_kernel_ms does not
+ * time it).  The unit table is copied from host memory on hip_stream, and
+ * the call waits for that copy (and so for the work queued before it).
+ * Every call on one GPU uses the same array: calls on one stream are
+ * ordered, but calls that overlap on one GPU (other streams, other
+ * threads) race and must not be made. */
+ee_status ee_batch_run_noalloc(ee_job* const* jobs, int32_t count, int32_t n_therm, const ee_launch_cfg* cfg,
+                               void* hip_stream);
+
 /* Per-job launch shape for ee_thermalize / ee_run_protocol (NULL = default). */
 ee_status ee_job_set_launch(ee_job* job, const ee_launch_cfg* cfg);
 

@@ -99,4 +99,6 @@ int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c
                              int work, void* stream);
 int ee_k_launch_stream_init(const ee::JobDev* job, int n_traj, int lanes, void* stream);
 int ee_k_launch_zero_work(const ee::JobDev* job, int n_traj, void* stream);
+size_t ee_k_scratch_bytes();
+int ee_k_scratch_ptr(void** out);
 }

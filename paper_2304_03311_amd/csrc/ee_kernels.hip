@@ -16,7 +16,10 @@
 //   integer max/min/sum of I_j, FP64 sum of exp(beta (I_j - I_max)/N),
 //   log-sum-exp, delete-one jackknife from prefix/suffix sums.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "ee_dd.hpp"
 #include "ee_internal.hpp"
@@ -1221,9 +1224,38 @@ __global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* con
 
 }  // namespace
 
+// Fixed device scratch of the allocation-free batch entry point: the queue
+// counter, the job table and the work units of one launch.  Each GPU holds
+// its own copy until the process ends.  In host code the array's name is
+// only a stand-in: its device address comes from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = size_t(2) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 extern "C" {
 
 int ee_k_max_lds_bytes() { return 160 * 1024 - 256; }
+
+size_t ee_k_scratch_bytes() { return kScratchBytes; }
+
+// Device address of the current device's copy of the scratch array, looked
+// up once per device (with that device current) and kept.
+int ee_k_scratch_ptr(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> ptrs;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)ptrs.size() <= dev) ptrs.resize(dev + 1, nullptr);
+  if (ptrs[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return 0;
+}
 
 static hipError_t set_lds_attr(const void* fn) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -353,50 +353,98 @@ ee_status check_cfg(const ee_launch_cfg* cfg) {
   return EE_OK;
 }
 
-ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launch_cfg& cfg,
-                     hipStream_t stream, Plan** out) {
-  auto P = new Plan();
-  P->jobs.assign(jobs, jobs + count);
-  P->n_therm = n_therm;
-  P->cfg = cfg;
-  P->dim = jobs[0]->d.dim;
+// Block size of a persistent launch over these jobs: the config's, else the
+// largest default block of the jobs; at least one lane per row word of
+// every job.
+int launch_block(ee_job* const* jobs, int count, const ee_launch_cfg& cfg) {
+  int block = 64;
   if (cfg.block_threads > 0) {
-    P->block = cfg.block_threads;
+    block = cfg.block_threads;
   } else {
-    P->block = 64;
-    for (int i = 0; i < count; ++i) P->block = std::max(P->block, default_block(jobs[i]->L, jobs[i]->d.n_replicas));
+    for (int i = 0; i < count; ++i) block = std::max(block, default_block(jobs[i]->L, jobs[i]->d.n_replicas));
   }
-  for (int i = 0; i < count; ++i) P->block = std::max(P->block, min_block(jobs[i]->L));
+  for (int i = 0; i < count; ++i) block = std::max(block, min_block(jobs[i]->L));
+  return block;
+}
+
+// LDS budget per workgroup: the config's (else the default), at least one
+// trajectory of every job.
+int lds_budget(ee_job* const* jobs, int count, const ee_launch_cfg& cfg) {
   int budget = cfg.lds_bytes > 0 ? cfg.lds_bytes : kDefaultLdsBudget;
   for (int i = 0; i < count; ++i) budget = std::max(budget, jobs[i]->L.traj_words * 4);
-  // units: per job, blocks of k trajectories; longest first
+  return budget;
+}
+
+// Relative cost of one unit of job j (k trajectories per workgroup of
+// `block` lanes): row iterations per half-sweep times sweeps.
+double unit_cost(const ee_job* j, int block, int k, int n_therm) {
+  const int T = block / k;
+  const int nrg = std::max(1, T / j->L.G);
+  const double iters = std::ceil((double)j->d.n_replicas * j->L.R / nrg);
+  return iters * (double)(n_therm + j->d.n_step);
+}
+
+// Persistent grid: as many workgroups of this shape as fit on the GPU at
+// once (or the config's count), at most one per unit.
+ee_status persistent_grid(int block, int lds, int n_units, const ee_launch_cfg& cfg, int* grid) {
+  const void* fn = nullptr;
+  const int rc = ee_k_sweep_kernel_ptr(&fn);
+  if (rc != 0) return fail(EE_EHIP, "kernel attribute: %s", hipGetErrorString((hipError_t)rc));
+  int per_cu = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds + ee::kSweepTailBytes);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  const int g = cfg.grid_blocks > 0 ? cfg.grid_blocks : device_info().cus * per_cu;
+  *grid = std::max(1, std::min(g, n_units));
+  return EE_OK;
+}
+
+// The work units of a persistent launch over these jobs: per job, blocks
+// of k trajectories (k LDS slots within the budget), sorted longest first.
+struct UnitPlan {
+  int block = 0, lds = 0, grid = 0;
+  std::vector<ee::Unit> units;
+};
+
+ee_status plan_units(ee_job* const* jobs, int count, int n_therm, const ee_launch_cfg& cfg, UnitPlan* out) {
+  out->block = launch_block(jobs, count, cfg);
+  const int budget = lds_budget(jobs, count, cfg);
   struct U { ee::Unit u; double cost; };
   std::vector<U> units;
   int lds_need = 0;
   for (int i = 0; i < count; ++i) {
     ee_job* j = jobs[i];
-    const int k = choose_slots(j->L, j->d.n_replicas, P->block, budget, j->d.n_traj);
+    const int k = choose_slots(j->L, j->d.n_replicas, out->block, budget, j->d.n_traj);
     lds_need = std::max(lds_need, k * j->L.traj_words * 4);
-    const int T = P->block / k;
-    const int nrg = std::max(1, T / j->L.G);
-    const double iters = std::ceil((double)j->d.n_replicas * j->L.R / nrg);
-    const double cost = iters * (double)(n_therm + j->d.n_step);
+    const double cost = unit_cost(j, out->block, k, n_therm);
     for (int j0 = 0; j0 < j->d.n_traj; j0 += k)
       units.push_back({ee::Unit{i, j0, std::min(k, j->d.n_traj - j0), k}, cost});
   }
   std::stable_sort(units.begin(), units.end(), [](const U& a, const U& b) { return a.cost > b.cost; });
-  P->lds = lds_need;
-  P->n_units = (int)units.size();
-  // persistent grid: as many workgroups as fit on the GPU at once
+  out->lds = lds_need;
+  out->units.resize(units.size());
+  for (size_t i = 0; i < units.size(); ++i) out->units[i] = units[i].u;
+  return persistent_grid(out->block, out->lds, (int)units.size(), cfg, &out->grid);
+}
+
+ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launch_cfg& cfg,
+                     hipStream_t stream, Plan** out) {
+  UnitPlan up;
+  ee_status st = plan_units(jobs, count, n_therm, cfg, &up);
+  if (st) return st;
+  auto P = new Plan();
+  P->jobs.assign(jobs, jobs + count);
+  P->n_therm = n_therm;
+  P->cfg = cfg;
+  P->dim = jobs[0]->d.dim;
+  P->block = up.block;
+  P->lds = up.lds;
+  P->grid = up.grid;
+  P->n_units = (int)up.units.size();
+  const std::vector<ee::Unit>& units = up.units;
   const void* fn = nullptr;
   int rc = ee_k_sweep_kernel_ptr(&fn);
   if (rc != 0) { delete P; return fail(EE_EHIP, "kernel attribute: %s", hipGetErrorString((hipError_t)rc)); }
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, P->block, P->lds + ee::kSweepTailBytes);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  const DeviceInfo di = device_info();
-  P->grid = cfg.grid_blocks > 0 ? cfg.grid_blocks : di.cus * per_cu;
-  P->grid = std::max(1, std::min(P->grid, P->n_units));
+  hipError_t e = hipSuccess;
   // device metadata
   const size_t off_tab = kAlign;
   const size_t off_units = align_up(off_tab + sizeof(void*) * count);
@@ -410,7 +458,7 @@ ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launc
   for (int i = 0; i < count; ++i)
     reinterpret_cast<const ee::JobDev**>(host.data() + off_tab)[i] = jobs[i]->dev_jobdev();
   for (size_t i = 0; i < units.size(); ++i)
-    reinterpret_cast<ee::Unit*>(host.data() + off_units)[i] = units[i].u;
+    reinterpret_cast<ee::Unit*>(host.data() + off_units)[i] = units[i];
   e = hipMemcpy(P->dev_buf, host.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) { delete P; return fail(EE_EHIP, "upload of batch plan: %s", hipGetErrorString(e)); }
   if (hipEventCreate(&P->ev_start) != hipSuccess || hipEventCreate(&P->ev_stop) != hipSuccess) {
@@ -466,6 +514,40 @@ ee_status build_plan(ee_job* const* jobs, int count, int n_therm, const ee_launc
   (void)stream;
   *out = P;
   return EE_OK;
+}
+
+// Checks shared by the batch entry points: every job freshly created, on
+// chip, listed once; the sweep counters fit.
+ee_status check_batch(ee_job* const* jobs, int count, int n_therm, const ee_launch_cfg* cfg) {
+  if (!jobs || count < 1) return fail(EE_EINVAL, "need at least one job");
+  if (n_therm < 0) return fail(EE_EINVAL, "n_therm must be >= 0");
+  ee_status s = check_cfg(cfg);
+  if (s) return s;
+  for (int i = 0; i < count; ++i) {
+    if (!jobs[i]) return fail(EE_EINVAL, "jobs[%d] is NULL", i);
+    if (jobs[i]->state != CREATED || jobs[i]->spins_exist)
+      return fail(EE_ESTATE, "jobs[%d] is not freshly created (use ee_job_reset)", i);
+    if (jobs[i]->streaming)
+      return fail(EE_EUNSUPPORTED, "jobs[%d] is too large for the on-chip batch kernel; run it with "
+                  "ee_thermalize / ee_run_protocol", i);
+    for (int k = 0; k < i; ++k)
+      if (jobs[k] == jobs[i]) return fail(EE_EINVAL, "jobs[%d] appears twice", i);
+    if ((int64_t)n_therm + jobs[i]->d.n_step > 0x7FFFFFFF) return fail(EE_EINVAL, "sweep counter overflow");
+  }
+  return EE_OK;
+}
+
+// Host state of jobs whose batch (sweeps + estimator) is enqueued on stream.
+void mark_batch_done(ee_job* const* jobs, int count, int n_therm, hipStream_t stream) {
+  for (int i = 0; i < count; ++i) {
+    ee_job* j = jobs[i];
+    j->spins_exist = true;
+    j->g = (int64_t)n_therm + j->d.n_step;
+    j->n_therm_total = n_therm;
+    j->state = DONE;
+    j->est_enqueued = true;
+    j->est_stream = stream;
+  }
 }
 
 ee_status run_plan(Plan* P, hipStream_t stream) {
@@ -716,22 +798,9 @@ ee_status ee_job_reset(ee_job* job) {
 ee_status ee_batch_run_cfg(ee_job* const* jobs, int32_t count, int32_t n_therm, const ee_launch_cfg* cfg,
                            void* hip_stream) {
   g_err.clear();
-  if (!jobs || count < 1) return fail(EE_EINVAL, "need at least one job");
-  if (n_therm < 0) return fail(EE_EINVAL, "n_therm must be >= 0");
-  ee_status s = check_cfg(cfg);
+  ee_status s = check_batch(jobs, count, n_therm, cfg);
   if (s) return s;
   ee_launch_cfg c = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1, 0};
-  for (int i = 0; i < count; ++i) {
-    if (!jobs[i]) return fail(EE_EINVAL, "jobs[%d] is NULL", i);
-    if (jobs[i]->state != CREATED || jobs[i]->spins_exist)
-      return fail(EE_ESTATE, "jobs[%d] is not freshly created (use ee_job_reset)", i);
-    if (jobs[i]->streaming)
-      return fail(EE_EUNSUPPORTED, "jobs[%d] is too large for the on-chip batch kernel; run it with "
-                  "ee_thermalize / ee_run_protocol", i);
-    for (int k = 0; k < i; ++k)
-      if (jobs[k] == jobs[i]) return fail(EE_EINVAL, "jobs[%d] appears twice", i);
-    if ((int64_t)n_therm + jobs[i]->d.n_step > 0x7FFFFFFF) return fail(EE_EINVAL, "sweep counter overflow");
-  }
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   // the job tables must be uploaded before the batch reads them
   for (int i = 0; i < count; ++i)
@@ -766,20 +835,55 @@ ee_status ee_batch_run_cfg(ee_job* const* jobs, int32_t count, int32_t n_therm, 
   s = run_plan(P, stream);
   if (s) return s;
   g_last_plan = P;
-  for (int i = 0; i < count; ++i) {
-    ee_job* j = jobs[i];
-    j->spins_exist = true;
-    j->g = (int64_t)n_therm + j->d.n_step;
-    j->n_therm_total = n_therm;
-    j->state = DONE;
-    j->est_enqueued = true;
-    j->est_stream = stream;
-  }
+  mark_batch_done(jobs, count, n_therm, stream);
   return EE_OK;
 }
 
 ee_status ee_batch_run(ee_job* const* jobs, int32_t count, int32_t n_therm, void* hip_stream) {
   return ee_batch_run_cfg(jobs, count, n_therm, nullptr, hip_stream);
+}
+
+ee_status ee_batch_run_noalloc(ee_job* const* jobs, int32_t count, int32_t n_therm, const ee_launch_cfg* cfg,
+                               void* hip_stream) {
+  g_err.clear();
+  ee_status s = check_batch(jobs, count, n_therm, cfg);
+  if (s) return s;
+  const ee_launch_cfg c = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1, 0};
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  UnitPlan up;
+  s = plan_units(jobs, count, n_therm, c, &up);
+  if (s) return s;
+  // the tables in the fixed scratch array: [queue counter][job table][units]
+  const size_t off_tab = kAlign;
+  const size_t off_units = align_up(off_tab + sizeof(void*) * count);
+  const size_t bytes = off_units + sizeof(ee::Unit) * up.units.size();
+  if (bytes > ee_k_scratch_bytes())
+    return fail(EE_EINVAL, "the batch needs %zu bytes of tables (%d jobs, %zu work units), more than the %zu-byte "
+                "scratch of the allocation-free entry point", bytes, count, up.units.size(), ee_k_scratch_bytes());
+  void* scr = nullptr;
+  int rc = ee_k_scratch_ptr(&scr);
+  if (rc) return fail(EE_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString((hipError_t)rc));
+  for (int i = 0; i < count; ++i)
+    if (jobs[i]->stream != stream) HIP_TRY(hipStreamSynchronize(jobs[i]->stream));
+  std::vector<uint8_t> host(bytes - off_tab);
+  for (int i = 0; i < count; ++i) reinterpret_cast<const ee::JobDev**>(host.data())[i] = jobs[i]->dev_jobdev();
+  std::memcpy(host.data() + (off_units - off_tab), up.units.data(), sizeof(ee::Unit) * up.units.size());
+  uint8_t* base = reinterpret_cast<uint8_t*>(scr);
+  int* queue = reinterpret_cast<int*>(base);
+  const ee::JobDev* const* jobtab = reinterpret_cast<const ee::JobDev* const*>(base + off_tab);
+  const ee::Unit* units = reinterpret_cast<const ee::Unit*>(base + off_units);
+  // stream-ordered after the previous user of the array on this stream; the
+  // host buffer must outlive the copy, so the call waits for it
+  HIP_TRY(hipMemcpyAsync(base + off_tab, host.data(), host.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  rc = ee_k_launch_queue_reset(queue, stream);
+  if (rc == 0)
+    rc = ee_k_launch_sweep(nullptr, 0, units, (int)up.units.size(), queue, jobtab, ee::kFlagInit | ee::kFlagProto,
+                           n_therm, 0, up.grid, up.block, up.lds, stream);
+  if (rc == 0) rc = ee_k_launch_estimate(jobtab, count, stream);
+  if (rc) return fail(EE_EHIP, "allocation-free batch launch: %s", hipGetErrorString((hipError_t)rc));
+  mark_batch_done(jobs, count, n_therm, stream);
+  return EE_OK;
 }
 
 ee_status ee_batch_kernel_ms(double* ms) {

@@ -65,6 +65,8 @@ _SIGS = {
     "ee_batch_run": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p],
     "ee_batch_run_cfg": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ee_launch_cfg),
                          ctypes.c_void_p],
+    "ee_batch_run_noalloc": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ee_launch_cfg),
+                             ctypes.c_void_p],
     "ee_job_set_launch": [ctypes.c_void_p, ctypes.POINTER(ee_launch_cfg)],
     "ee_batch_kernel_ms": [ctypes.POINTER(ctypes.c_double)],
     "ee_job_destroy": [ctypes.c_void_p],
@@ -168,6 +170,13 @@ def ee_batch_run(jobs: list[int], n_therm: int, stream: int, cfg=None) -> None:
     c = _cfg(cfg)
     _check("ee_batch_run_cfg", lib().ee_batch_run_cfg(arr, len(jobs), n_therm,
                                                        ctypes.byref(c) if c is not None else None, stream))
+
+
+def ee_batch_run_noalloc(jobs: list[int], n_therm: int, stream: int, cfg=None) -> None:
+    arr = (ctypes.c_void_p * len(jobs))(*jobs)
+    c = _cfg(cfg)
+    _check("ee_batch_run_noalloc", lib().ee_batch_run_noalloc(arr, len(jobs), n_therm,
+                                                               ctypes.byref(c) if c is not None else None, stream))
 
 
 def ee_job_set_launch(job: int, cfg) -> None:
@@ -280,3 +289,7 @@ class Job:
 
 def batch_run(jobs: list[Job], n_therm: int, stream=None, cfg=None) -> None:
     ee_batch_run([j.handle for j in jobs], n_therm, _stream_handle(stream), cfg)
+
+
+def batch_run_noalloc(jobs: list[Job], n_therm: int, stream=None, cfg=None) -> None:
+    ee_batch_run_noalloc([j.handle for j in jobs], n_therm, _stream_handle(stream), cfg)
