@@ -104,17 +104,24 @@ def cpu_baseline(n_traj_sample: int, procs: int | None = None) -> dict:
 
 
 def serving_run(n_jobs: int, rate: float = 200.0) -> dict:
-    """Poisson stream at `rate` jobs/s through the continuous-batching server."""
+    """The serving loop on a Poisson stream of n_jobs requests at `rate`
+    jobs/s (about 70% of capacity), then the same requests all at once
+    (saturation).  Delivered attempts/ns, its HBM-roofline fraction on the
+    2 bytes per attempt, and p50/p99 arrival-to-result latency."""
     from paper_2304_03311_amd import serve, workloads
     stream = workloads.serving_stream(n_jobs, rate, seed=1, **workloads.SERVE_MIX)
-    reqs = serve.requests_from_stream(stream)
     offered = sum(s.n_traj * s.sites * (workloads.N_THERM + s.n_step) for _, s in stream) / stream[-1][0]
-    srv = serve.Server(hbm_budget_bytes=workloads.SERVE_HBM_BUDGET, slots=workloads.SERVE_SLOTS,
-                       n_therm=workloads.N_THERM)
-    srv.run(reqs, realtime=True)
-    out = srv.stats.summary()
-    out.update(rate_jobs_per_s=rate, offered_attempts_per_ns=offered / 1e9, mix=workloads.SERVE_MIX,
-               hbm_budget_bytes=workloads.SERVE_HBM_BUDGET, slots=workloads.SERVE_SLOTS)
+    out = {"rate_jobs_per_s": rate, "offered_attempts_per_ns": offered / 1e9, "mix": workloads.SERVE_MIX,
+           "launch": workloads.SERVE_LAUNCH, "hbm_budget_bytes": workloads.SERVE_HBM_BUDGET,
+           "jobs_streamed_from_hbm": sum(1 for _, s in stream if s.dim == 3 and s.lx >= 48)}
+    for name, realtime in (("poisson", True), ("saturation", False)):
+        srv = serve.Server(hbm_budget_bytes=workloads.SERVE_HBM_BUDGET, n_therm=workloads.N_THERM,
+                           launch=workloads.SERVE_LAUNCH)
+        srv.run(serve.requests_from_stream(stream), realtime=realtime)
+        srv.close()
+        r = srv.stats.summary()
+        r["hbm_frac"] = hbm_frac(r["attempts_per_ns"] * 1e9, 1.0)
+        out[name] = r
     return out
 
 
@@ -208,10 +215,12 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=32, help="oracle trajectories timed for cpu_baseline")
     ap.add_argument("--per-job", action="store_true", help="also time the per-job launch path")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency) measurement")
-    ap.add_argument("--serve-jobs", type=int, default=400)
+    ap.add_argument("--serve-jobs", type=int, default=2000)
     ap.add_argument("--tune", action="store_true",
                     help="re-tune the headline set's launch shape instead of taking the shipped tuned one")
     ap.add_argument("--no-configs", action="store_true", help="skip the c1/c3/c4 job sets")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving measurement and print its JSON")
     ap.add_argument("--stream-only", action="store_true",
                     help="run only the HBM-streaming measurement (3D 96^3) and print its JSON (profiled runs)")
     ap.add_argument("--launch", default=None,
@@ -236,6 +245,9 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.stream_only:
         print(json.dumps({"streaming_path": streaming_run()}), flush=True)
+        return 0
+    if args.serve_only:
+        print(json.dumps({"serving": serving_run(args.serve_jobs)}), flush=True)
         return 0
     specs = workloads.config2_jobs()
     stream = torch.cuda.current_stream()

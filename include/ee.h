@@ -137,6 +137,11 @@ typedef struct ee_job ee_job; /* opaque host-side handle */
  * words (lx/2 > 4096 sites).  Such lattices are streamed from HBM in INT8. */
 ee_status ee_job_footprint(const ee_job_desc* desc, size_t* bytes);
 
+/* *on_chip = 1 if the job's trajectories run on chip (one trajectory fits
+ * a workgroup's LDS and a row has at most 1024 words), 0 if they are
+ * streamed from HBM (per-job path only).  No device work. */
+ee_status ee_job_on_chip(const ee_job_desc* desc, int32_t* on_chip);
+
 /* Validate desc, build the geometry and the uint32 threshold tables on the
  * host (FP64 libm exp, Sec. 3 couplings), and enqueue their upload into the
  * arena on hip_stream.  arena: device pointer, 256-byte aligned, at least
@@ -229,6 +234,66 @@ ee_status ee_batch_run_cfg(ee_job* const* jobs, int32_t count, int32_t n_therm,
  * threads) race and must not be made. */
 ee_status ee_batch_run_noalloc(ee_job* const* jobs, int32_t count, int32_t n_therm, const ee_launch_cfg* cfg,
                                void* hip_stream);
+
+/*
+ * Continuous batching (serving).  A server runs the persistent sweep kernel
+ * over the work units (blocks of trajectories) of the jobs submitted to it,
+ * in chunks.  A job's units belong to its launch class: the job's own shape
+ * if ee_job_set_launch gave block_threads and lds_bytes, else the server's.
+ * Units queue per class in submission order; whenever one of the server's
+ * max_inflight launch slots is free, the class holding the oldest waiting
+ * unit fills a chunk (at most chunk_units, or twice the workgroups of its
+ * shape that fit on the GPU at once) that runs in one persistent launch on
+ * that slot's stream.  Chunks overlap on the device, so jobs submitted while
+ * others run start as soon as a slot frees, and each chunk's workgroups fill
+ * the CUs the previous chunk's tail leaves idle.  When every unit of a job
+ * has run, its estimator runs on the server's service stream, and
+ * ee_server_poll then reports the job DONE (its result is read with
+ * ee_estimate).  Results are bit-identical to the per-job and batch paths,
+ * whatever else is on the server.  The server owns its streams (default
+ * priority, non-blocking), one device table buffer and one pinned staging
+ * buffer per slot.  One server must not be used from two threads at once.
+ */
+typedef struct ee_server ee_server;
+
+/* cfg: the default block_threads (0 = 256) and lds_bytes (0 = default) of
+ * chunk launches, grid_blocks as for ee_batch_run_cfg; use_graph is
+ * ignored.  n_therm: thermalisation sweeps of every job.  max_inflight:
+ * launch slots (1..8).  chunk_units: work units per launch at most (0 =
+ * 8192, and per class twice its workgroups that fit on the GPU at once). */
+ee_status ee_server_create(const ee_launch_cfg* cfg, int32_t n_therm, int32_t max_inflight, int32_t chunk_units,
+                           ee_server** out);
+
+/* Queue a CREATED job (fresh, on chip; EE_EUNSUPPORTED for jobs on the
+ * HBM-streaming path), then launch chunks on free slots.  Does not wait on
+ * the host: the chunks that run the job wait on the device for its table
+ * upload on its own stream.  The job is then SERVED: every other call on it
+ * returns EE_ESTATE (ee_job_destroy included) until a poll has reported
+ * it. */
+ee_status ee_server_submit(ee_server* srv, ee_job* job);
+
+/* Non-blocking progress: collect finished chunks, launch estimators of jobs
+ * whose units have all run, refill free slots.  Writes up to cap jobs
+ * whose estimate has completed to done[] (in completion order) and their
+ * number to *n_done; those jobs are DONE, and later reads of them run on
+ * their own streams. */
+ee_status ee_server_poll(ee_server* srv, ee_job** done, int32_t cap, int32_t* n_done);
+
+/* The server's service stream (a hipStream_t), on which it launches the
+ * estimators.  Creating the jobs for a server on this stream (ee_job_create)
+ * keeps their table uploads off the chunk streams: with more streams than
+ * the device has hardware queues, streams share in-order queues, and an
+ * upload queued behind a long chunk kernel would hold up ee_server_submit.
+ * Owned by the server. */
+ee_status ee_server_stream(ee_server* srv, void** stream);
+
+/* Jobs submitted and not yet returned by ee_server_poll. */
+ee_status ee_server_open_jobs(ee_server* srv, int32_t* n);
+
+/* Wait for the server's device work and free it.  Jobs not yet returned by
+ * a poll become DONE if their estimator was launched (it has completed),
+ * else go back to CREATED. */
+ee_status ee_server_destroy(ee_server* srv);
 
 /* Per-job launch shape for ee_thermalize / ee_run_protocol (NULL = default). */
 ee_status ee_job_set_launch(ee_job* job, const ee_launch_cfg* cfg);

@@ -13,7 +13,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <list>
+#include <unordered_map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -45,7 +47,7 @@ ee_status fail(ee_status s, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
-enum State { CREATED = 0, DONE = 2 };
+enum State { CREATED = 0, SERVED = 1, DONE = 2 };  // SERVED: submitted to a server, not yet done
 
 struct Layout {
   size_t off_jobdev, off_selfptr, off_result, off_ramp, off_work, off_spins, total;
@@ -594,6 +596,15 @@ ee_status ee_job_footprint(const ee_job_desc* desc, size_t* bytes) {
   return EE_OK;
 }
 
+ee_status ee_job_on_chip(const ee_job_desc* desc, int32_t* on_chip) {
+  g_err.clear();
+  if (!on_chip) return fail(EE_EINVAL, "on_chip is NULL");
+  ee_status s = validate(desc);
+  if (s) return s;
+  *on_chip = fits_on_chip(layout_of(desc)) ? 1 : 0;
+  return EE_OK;
+}
+
 ee_status ee_job_create(const ee_job_desc* desc, void* dev_arena, size_t arena_bytes, void* hip_stream,
                         ee_job** out) {
   g_err.clear();
@@ -673,6 +684,7 @@ ee_status ee_job_set_launch(ee_job* job, const ee_launch_cfg* cfg) {
   if (!job) return fail(EE_EINVAL, "job is NULL");
   ee_status s = check_cfg(cfg);
   if (s) return s;
+  if (job->state == SERVED) return fail(EE_ESTATE, "the job is on a server that has not reported it done");
   const bool force_stream = cfg && (cfg->flags & EE_LAUNCH_STREAMING);
   if (force_stream && job->d.spin_format != EE_SPINS_INT8)
     return fail(EE_EUNSUPPORTED, "the streaming path needs EE_SPINS_INT8 storage");
@@ -748,6 +760,7 @@ ee_status ee_job_read_work(ee_job* job, int64_t* host_I, int32_t count) {
 ee_status ee_job_read_spins(ee_job* job, int8_t* host, size_t count) {
   g_err.clear();
   if (!job || (!host && count > 0)) return fail(EE_EINVAL, "NULL argument");
+  if (job->state == SERVED) return fail(EE_ESTATE, "the job is on a server that has not reported it done");
   if (!job->spins_exist) return fail(EE_ESTATE, "no spins before ee_thermalize");
   const ee_job_desc& d = job->d;
   const size_t per = (size_t)d.n_replicas * d.lt * d.ly * d.lx;
@@ -787,6 +800,7 @@ ee_status ee_job_read_spins(ee_job* job, int8_t* host, size_t count) {
 ee_status ee_job_reset(ee_job* job) {
   g_err.clear();
   if (!job) return fail(EE_EINVAL, "job is NULL");
+  if (job->state == SERVED) return fail(EE_ESTATE, "the job is on a server that has not reported it done");
   job->state = CREATED;
   job->spins_exist = false;
   job->g = 0;
@@ -901,10 +915,396 @@ ee_status ee_batch_kernel_ms(double* ms) {
 ee_status ee_job_destroy(ee_job* job) {
   g_err.clear();
   if (!job) return EE_OK;
+  if (job->state == SERVED) return fail(EE_ESTATE, "the job is on a server that has not reported it done");
   drop_plans_with(job);
   (void)hipStreamSynchronize(job->stream);
   if (job->est_stream != job->stream) (void)hipStreamSynchronize(job->est_stream);
   delete job;
+  return EE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Continuous batching (serving): the chunk scheduler behind ee_server_*.
+//
+// A submitted job is split into work units (blocks of k trajectories, as in
+// a batch) of its launch class: the job's own launch shape (ee_job_set_launch)
+// or the server's.  Units queue on the host per class, in submission order.
+// Whenever one of the server's launch slots is free and units are waiting,
+// the class whose oldest unit is the oldest overall fills a chunk (at most
+// its chunk size) and one persistent sweep kernel of that class's shape runs
+// it on the slot's stream.  Several slots keep chunks in flight, so a
+// chunk's workgroups fill the CUs the previous chunk's tail leaves idle,
+// and units of jobs submitted while others run start as soon as a slot
+// frees.  A job's table upload (on its own stream) is awaited on the device
+// by the chunks that need it, not on the host.  When every unit of a job has
+// run (the host sees its chunks' events), the job's estimator is launched on
+// the server's service stream; ee_server_poll reports the job once that
+// launch has completed.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct SrvJob {
+  ee_job* job = nullptr;
+  int units_left = 0;
+  hipEvent_t uploaded = nullptr;  // recorded on the job's stream at submission
+  bool upload_seen = false;       // the host has seen that event complete
+};
+
+struct SrvUnit {
+  int id;  // index into ee_server::jobs
+  int j0, count, k;
+  double cost;
+  uint64_t seq;  // submission order
+};
+
+struct SrvClass {
+  int block = 0, budget = 0, chunk_units = 0;
+  std::deque<SrvUnit> pending;
+};
+
+struct SrvSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  uint8_t* dev = nullptr;   // [queue counter][job table][units]
+  uint8_t* host = nullptr;  // pinned staging of the same bytes
+  bool busy = false;
+  std::vector<std::pair<int, int>> per_job;  // (job id, units of it in the chunk)
+};
+
+struct SrvEst {
+  hipEvent_t ev;
+  std::vector<int> ids;
+};
+
+}  // namespace
+
+struct ee_server {
+  ee_launch_cfg cfg{};
+  int n_therm = 0;
+  int max_chunk = 0;  // units per chunk at most (slot buffer capacity)
+  size_t off_tab = 0, off_units = 0, bytes = 0;
+  std::vector<SrvSlot> slots;
+  std::vector<SrvClass> classes;
+  uint64_t seq = 0;
+  std::vector<SrvJob> jobs;  // by id; ids of reported jobs are reused
+  std::vector<int> free_ids;
+  hipStream_t est_stream = nullptr;
+  std::deque<SrvEst> est;  // estimator launches in flight, in order
+  std::vector<hipEvent_t> spare_events;
+  std::deque<int> ready;  // done, not yet returned by ee_server_poll
+  int open_jobs = 0;      // submitted, not yet returned
+};
+
+namespace {
+
+ee_status server_event(ee_server* S, hipEvent_t* ev) {
+  if (!S->spare_events.empty()) {
+    *ev = S->spare_events.back();
+    S->spare_events.pop_back();
+    return EE_OK;
+  }
+  HIP_TRY(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+  return EE_OK;
+}
+
+void server_free(ee_server* S) {
+  for (SrvSlot& sl : S->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.dev) (void)hipFree(sl.dev);
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  if (S->est_stream) (void)hipStreamSynchronize(S->est_stream);
+  for (SrvEst& e : S->est) (void)hipEventDestroy(e.ev);
+  for (hipEvent_t e : S->spare_events) (void)hipEventDestroy(e);
+  for (SrvJob& sj : S->jobs)
+    if (sj.uploaded) (void)hipEventDestroy(sj.uploaded);
+  if (S->est_stream) (void)hipStreamDestroy(S->est_stream);
+  delete S;
+}
+
+// Launch the next chunk on a free slot: units of the class holding the
+// oldest waiting unit, longest first within the chunk.
+ee_status server_launch(ee_server* S, SrvSlot& sl) {
+  SrvClass* C = nullptr;
+  for (SrvClass& c : S->classes)
+    if (!c.pending.empty() && (!C || c.pending.front().seq < C->pending.front().seq)) C = &c;
+  if (!C) return EE_OK;
+  const int take = std::min<int>(C->chunk_units, (int)C->pending.size());
+  std::vector<SrvUnit> chunk(C->pending.begin(), C->pending.begin() + take);
+  C->pending.erase(C->pending.begin(), C->pending.begin() + take);
+  std::stable_sort(chunk.begin(), chunk.end(), [](const SrvUnit& a, const SrvUnit& b) { return a.cost > b.cost; });
+  std::unordered_map<int, int> local;  // job id -> index in the chunk's job table
+  sl.per_job.clear();
+  std::memset(sl.host, 0, S->off_tab);  // queue counter = 0
+  const ee::JobDev** tab = reinterpret_cast<const ee::JobDev**>(sl.host + S->off_tab);
+  ee::Unit* units = reinterpret_cast<ee::Unit*>(sl.host + S->off_units);
+  int block = C->block, lds = 0;
+  for (int i = 0; i < take; ++i) {
+    const SrvUnit& u = chunk[i];
+    SrvJob& sj = S->jobs[u.id];
+    auto it = local.find(u.id);
+    if (it == local.end()) {
+      it = local.emplace(u.id, (int)sl.per_job.size()).first;
+      tab[it->second] = sj.job->dev_jobdev();
+      sl.per_job.emplace_back(u.id, 0);
+      block = std::max(block, min_block(sj.job->L));
+      if (!sj.upload_seen) {
+        const hipError_t q = hipEventQuery(sj.uploaded);
+        if (q == hipSuccess) {
+          sj.upload_seen = true;
+        } else if (q == hipErrorNotReady) {
+          HIP_TRY(hipStreamWaitEvent(sl.stream, sj.uploaded, 0));
+        } else {
+          return fail(EE_EHIP, "job upload: %s", hipGetErrorString(q));
+        }
+      }
+    }
+    sl.per_job[it->second].second += 1;
+    units[i] = ee::Unit{it->second, u.j0, u.count, u.k};
+    lds = std::max(lds, u.k * sj.job->L.traj_words * 4);
+  }
+  int grid = 0;
+  ee_status s = persistent_grid(block, lds, take, S->cfg, &grid);
+  if (s) return s;
+  int* queue = reinterpret_cast<int*>(sl.dev);
+  HIP_TRY(hipMemcpyAsync(sl.dev, sl.host, S->off_units + sizeof(ee::Unit) * take, hipMemcpyHostToDevice, sl.stream));
+  const int rc = ee_k_launch_sweep(nullptr, 0, reinterpret_cast<const ee::Unit*>(sl.dev + S->off_units), take, queue,
+                                   reinterpret_cast<const ee::JobDev* const*>(sl.dev + S->off_tab),
+                                   ee::kFlagInit | ee::kFlagProto, S->n_therm, 0, grid, block, lds, sl.stream);
+  if (rc) return fail(EE_EHIP, "server chunk launch: %s", hipGetErrorString((hipError_t)rc));
+  HIP_TRY(hipEventRecord(sl.done, sl.stream));
+  sl.busy = true;
+  return EE_OK;
+}
+
+bool server_has_pending(const ee_server* S) {
+  for (const SrvClass& c : S->classes)
+    if (!c.pending.empty()) return true;
+  return false;
+}
+
+// Collect finished chunks, launch the estimators of jobs whose last unit
+// ran, move finished estimators to the ready list, and refill free slots.
+ee_status server_progress(ee_server* S) {
+  std::vector<int> finished;
+  for (SrvSlot& sl : S->slots) {
+    if (!sl.busy) continue;
+    const hipError_t q = hipEventQuery(sl.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return fail(EE_EHIP, "server chunk: %s", hipGetErrorString(q));
+    for (const auto& pj : sl.per_job) {
+      SrvJob& sj = S->jobs[pj.first];
+      sj.units_left -= pj.second;
+      if (sj.units_left == 0) finished.push_back(pj.first);
+    }
+    sl.busy = false;
+  }
+  if (!finished.empty()) {
+    for (int id : finished) {
+      ee_job* j = S->jobs[id].job;
+      const int rc = ee_k_launch_estimate(j->dev_selfptr(), 1, S->est_stream);
+      if (rc) return fail(EE_EHIP, "server estimator launch: %s", hipGetErrorString((hipError_t)rc));
+      // the job stays SERVED until a poll returns it
+      j->spins_exist = true;
+      j->g = (int64_t)S->n_therm + j->d.n_step;
+      j->n_therm_total = S->n_therm;
+      j->est_enqueued = true;
+    }
+    hipEvent_t ev = nullptr;
+    ee_status s = server_event(S, &ev);
+    if (s) return s;
+    HIP_TRY(hipEventRecord(ev, S->est_stream));
+    S->est.push_back(SrvEst{ev, finished});
+  }
+  while (!S->est.empty()) {
+    const hipError_t q = hipEventQuery(S->est.front().ev);
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) return fail(EE_EHIP, "server estimator: %s", hipGetErrorString(q));
+    for (int id : S->est.front().ids) S->ready.push_back(id);
+    S->spare_events.push_back(S->est.front().ev);
+    S->est.pop_front();
+  }
+  for (SrvSlot& sl : S->slots) {
+    if (!server_has_pending(S)) break;
+    if (sl.busy) continue;
+    ee_status s = server_launch(S, sl);
+    if (s) return s;
+  }
+  return EE_OK;
+}
+
+// The launch class of a job: its own shape if ee_job_set_launch gave block
+// and LDS, else the server's.
+ee_status server_class(ee_server* S, const ee_job* job, SrvClass** out) {
+  int block = S->cfg.block_threads > 0 ? S->cfg.block_threads : 256;
+  int budget = S->cfg.lds_bytes > 0 ? S->cfg.lds_bytes : kDefaultLdsBudget;
+  if (job->cfg.block_threads > 0) block = job->cfg.block_threads;
+  if (job->cfg.lds_bytes > 0) budget = job->cfg.lds_bytes;
+  for (SrvClass& c : S->classes)
+    if (c.block == block && c.budget == budget) {
+      *out = &c;
+      return EE_OK;
+    }
+  SrvClass c;
+  c.block = block;
+  c.budget = budget;
+  int grid = 0;
+  ee_status s = persistent_grid(block, budget, 1 << 30, S->cfg, &grid);
+  if (s) return s;
+  c.chunk_units = std::min(S->max_chunk, 2 * grid);
+  S->classes.push_back(c);
+  *out = &S->classes.back();
+  return EE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ee_status ee_server_create(const ee_launch_cfg* cfg, int32_t n_therm, int32_t max_inflight, int32_t chunk_units,
+                           ee_server** out) {
+  g_err.clear();
+  if (!out) return fail(EE_EINVAL, "out is NULL");
+  ee_status s = check_cfg(cfg);
+  if (s) return s;
+  if (n_therm < 0) return fail(EE_EINVAL, "n_therm must be >= 0");
+  if (max_inflight < 1 || max_inflight > 8) return fail(EE_EINVAL, "max_inflight must be in [1, 8]");
+  if (chunk_units < 0 || chunk_units > (1 << 20)) return fail(EE_EINVAL, "chunk_units must be in [0, 2^20]");
+  ee_server* S = new ee_server();
+  S->cfg = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1, 0};
+  S->n_therm = n_therm;
+  S->max_chunk = chunk_units > 0 ? chunk_units : 8192;
+  S->off_tab = kAlign;
+  S->off_units = align_up(S->off_tab + sizeof(void*) * S->max_chunk);
+  S->bytes = S->off_units + sizeof(ee::Unit) * S->max_chunk;
+  S->slots.resize(max_inflight);
+  for (SrvSlot& sl : S->slots) {
+    hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.dev), S->bytes);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.host), S->bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      server_free(S);
+      return fail(EE_EHIP, "server set-up: %s", hipGetErrorString(e));
+    }
+  }
+  hipError_t e = hipStreamCreateWithFlags(&S->est_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    server_free(S);
+    return fail(EE_EHIP, "server set-up: %s", hipGetErrorString(e));
+  }
+  *out = S;
+  return EE_OK;
+}
+
+ee_status ee_server_submit(ee_server* S, ee_job* job) {
+  g_err.clear();
+  if (!S || !job) return fail(EE_EINVAL, "NULL argument");
+  ee_job* one[1] = {job};
+  ee_status s = check_batch(one, 1, S->n_therm, nullptr);
+  if (s) return s;
+  SrvClass* C = nullptr;
+  s = server_class(S, job, &C);
+  if (s) return s;
+  const int block = std::max(C->block, min_block(job->L));
+  const int k = choose_slots(job->L, job->d.n_replicas, block, std::max(C->budget, job->L.traj_words * 4),
+                             job->d.n_traj);
+  const double cost = unit_cost(job, block, k, S->n_therm);
+  hipEvent_t ev = nullptr;
+  s = server_event(S, &ev);
+  if (s) return s;
+  // the chunks that run the job wait (on the device) for its table upload
+  const hipError_t e = hipEventRecord(ev, job->stream);
+  if (e != hipSuccess) {
+    S->spare_events.push_back(ev);
+    return fail(EE_EHIP, "hipEventRecord: %s", hipGetErrorString(e));
+  }
+  int id;
+  if (!S->free_ids.empty()) {
+    id = S->free_ids.back();
+    S->free_ids.pop_back();
+  } else {
+    id = (int)S->jobs.size();
+    S->jobs.emplace_back();
+  }
+  SrvJob& sj = S->jobs[id];
+  sj.job = job;
+  sj.units_left = (job->d.n_traj + k - 1) / k;
+  sj.uploaded = ev;
+  sj.upload_seen = false;
+  for (int j0 = 0; j0 < job->d.n_traj; j0 += k)
+    C->pending.push_back(SrvUnit{id, j0, std::min(k, job->d.n_traj - j0), k, cost, S->seq++});
+  job->state = SERVED;
+  S->open_jobs += 1;
+  return server_progress(S);
+}
+
+ee_status ee_server_poll(ee_server* S, ee_job** done, int32_t cap, int32_t* n_done) {
+  g_err.clear();
+  if (!S || !n_done || (cap > 0 && !done)) return fail(EE_EINVAL, "NULL argument");
+  *n_done = 0;
+  ee_status s = server_progress(S);
+  if (s) return s;
+  while (*n_done < cap && !S->ready.empty()) {
+    const int id = S->ready.front();
+    S->ready.pop_front();
+    // its estimate has completed: later reads use the job's own stream, not
+    // the server's (which ee_server_destroy frees)
+    SrvJob& sj = S->jobs[id];
+    ee_job* j = sj.job;
+    j->state = DONE;
+    j->est_stream = j->stream;
+    done[(*n_done)++] = j;
+    S->spare_events.push_back(sj.uploaded);
+    sj = SrvJob{};
+    S->free_ids.push_back(id);
+    S->open_jobs -= 1;
+  }
+  return EE_OK;
+}
+
+ee_status ee_server_stream(ee_server* S, void** stream) {
+  g_err.clear();
+  if (!S || !stream) return fail(EE_EINVAL, "NULL argument");
+  *stream = reinterpret_cast<void*>(S->est_stream);
+  return EE_OK;
+}
+
+ee_status ee_server_open_jobs(ee_server* S, int32_t* n) {
+  g_err.clear();
+  if (!S || !n) return fail(EE_EINVAL, "NULL argument");
+  *n = S->open_jobs;
+  return EE_OK;
+}
+
+ee_status ee_server_destroy(ee_server* S) {
+  g_err.clear();
+  if (!S) return EE_OK;
+  for (SrvSlot& sl : S->slots)
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+  if (S->est_stream) (void)hipStreamSynchronize(S->est_stream);
+  // jobs not yet reported: those whose estimator was launched (it has now
+  // completed) are DONE; the others go back to CREATED (their partial device
+  // state is redrawn by the next run).  None keeps the server's stream.
+  for (SrvJob& sj : S->jobs) {
+    ee_job* j = sj.job;
+    if (!j || j->state != SERVED) continue;
+    if (sj.uploaded) (void)hipEventSynchronize(sj.uploaded);
+    if (j->est_enqueued) {
+      j->state = DONE;
+    } else {
+      j->state = CREATED;
+      j->spins_exist = false;
+      j->g = 0;
+      j->n_therm_total = 0;
+    }
+    j->est_stream = j->stream;
+  }
+  server_free(S);
   return EE_OK;
 }
 

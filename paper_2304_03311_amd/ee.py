@@ -54,6 +54,7 @@ class EEError(RuntimeError):
 _lib = None
 _SIGS = {
     "ee_job_footprint": [ctypes.POINTER(ee_job_desc), ctypes.POINTER(ctypes.c_size_t)],
+    "ee_job_on_chip": [ctypes.POINTER(ee_job_desc), ctypes.POINTER(ctypes.c_int32)],
     "ee_job_create": [ctypes.POINTER(ee_job_desc), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                       ctypes.POINTER(ctypes.c_void_p)],
     "ee_thermalize": [ctypes.c_void_p, ctypes.c_int32],
@@ -70,6 +71,13 @@ _SIGS = {
     "ee_job_set_launch": [ctypes.c_void_p, ctypes.POINTER(ee_launch_cfg)],
     "ee_batch_kernel_ms": [ctypes.POINTER(ctypes.c_double)],
     "ee_job_destroy": [ctypes.c_void_p],
+    "ee_server_create": [ctypes.POINTER(ee_launch_cfg), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                         ctypes.POINTER(ctypes.c_void_p)],
+    "ee_server_submit": [ctypes.c_void_p, ctypes.c_void_p],
+    "ee_server_poll": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "ee_server_open_jobs": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)],
+    "ee_server_stream": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "ee_server_destroy": [ctypes.c_void_p],
 }
 EXPORTED = list(_SIGS) + ["ee_last_error", "ee_version", "ee_build_id"]
 
@@ -115,6 +123,12 @@ def ee_job_footprint(desc: ee_job_desc) -> int:
     out = ctypes.c_size_t()
     _check("ee_job_footprint", lib().ee_job_footprint(ctypes.byref(desc), ctypes.byref(out)))
     return int(out.value)
+
+
+def ee_job_on_chip(desc: ee_job_desc) -> bool:
+    out = ctypes.c_int32()
+    _check("ee_job_on_chip", lib().ee_job_on_chip(ctypes.byref(desc), ctypes.byref(out)))
+    return bool(out.value)
 
 
 def ee_job_create(desc: ee_job_desc, arena_ptr: int, arena_bytes: int, stream: int) -> int:
@@ -194,6 +208,41 @@ def ee_job_destroy(job: int) -> None:
     _check("ee_job_destroy", lib().ee_job_destroy(job))
 
 
+def ee_server_create(cfg, n_therm: int, max_inflight: int = 2, chunk_units: int = 0) -> int:
+    c = _cfg(cfg)
+    h = ctypes.c_void_p()
+    _check("ee_server_create", lib().ee_server_create(ctypes.byref(c) if c is not None else None, n_therm,
+                                                      max_inflight, chunk_units, ctypes.byref(h)))
+    return h.value
+
+
+def ee_server_submit(srv: int, job: int) -> None:
+    _check("ee_server_submit", lib().ee_server_submit(srv, job))
+
+
+def ee_server_poll(srv: int, cap: int = 256) -> list[int]:
+    arr = (ctypes.c_void_p * cap)()
+    n = ctypes.c_int32()
+    _check("ee_server_poll", lib().ee_server_poll(srv, arr, cap, ctypes.byref(n)))
+    return [arr[i] for i in range(n.value)]
+
+
+def ee_server_stream(srv: int) -> int:
+    h = ctypes.c_void_p()
+    _check("ee_server_stream", lib().ee_server_stream(srv, ctypes.byref(h)))
+    return int(h.value or 0)
+
+
+def ee_server_open_jobs(srv: int) -> int:
+    n = ctypes.c_int32()
+    _check("ee_server_open_jobs", lib().ee_server_open_jobs(srv, ctypes.byref(n)))
+    return int(n.value)
+
+
+def ee_server_destroy(srv: int) -> None:
+    _check("ee_server_destroy", lib().ee_server_destroy(srv))
+
+
 def ee_version() -> str:
     return lib().ee_version().decode()
 
@@ -237,6 +286,9 @@ class JobSpec:
 
 
 def _stream_handle(stream) -> int:
+    """A torch stream, a raw hipStream_t (int), or None (torch's current stream)."""
+    if isinstance(stream, int):
+        return stream
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)

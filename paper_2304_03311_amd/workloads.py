@@ -30,21 +30,24 @@ BETA_C_2D = 0.5 * math.log(1.0 + math.sqrt(2.0))  # Sec. 4
 BETA_3D = 0.2216546                                 # Sec. 5 (beta_c = 0.221654626(5))
 N_THERM = 100
 
-# launch shape of the headline set (2D 64x64, 64 jobs x 1024 trajectories):
-# one 64-thread workgroup (one wave) per trajectory, which the sweep over
-# the tuner's shapes and more (64..1024 threads, one to sixteen trajectories
-# per workgroup) measured fastest: each wave owns a whole trajectory, so its
-# barriers wait for no other wave
+# launch shape of the headline set (2D 64x64, 64 jobs x 1024 trajectories)
+# when no tuned shape is at hand: one 64-thread workgroup (one wave) per
+# trajectory, the tuner's choice on an MI355X (each wave owns a whole
+# trajectory, so its barriers wait for no other wave)
 BENCH_LAUNCH = {"block_threads": 64, "lds_bytes": 8192, "grid_blocks": 0, "use_graph": 1, "flags": 0}
 
-# serving benchmark: size mix of the Poisson stream (tuned to about 60% of the
-# per-job path's measured capacity at 200 jobs/s), resident-job slots and the
-# HBM admission budget (288 GB of HBM3E minus a reserve for the rest of the
-# process)
-SERVE_MIX = {"max_l3": 96, "n_traj_choices": (64, 128, 256), "n_step_choices": (500, 1000),
-             "large_n_traj": (16, 32)}
-SERVE_SLOTS = 16
+# serving benchmark: size mix of the Poisson stream at 200 jobs/s (n_t up to
+# 4096; the mix sets the offered load, about 70% of the served path's
+# measured capacity), the HBM admission budget (288 GB of HBM3E minus a
+# reserve for the rest of the process) and the launch shapes of the server's
+# chunk launches by dimension: 2D lattices in one-wave workgroups of up to
+# 4 KiB (the tuner's shapes for the 2D sets), 3D in 512-thread workgroups
+# (the tuner's shape for the 3D-heavy 24-job set)
+SERVE_MIX = {"max_l3": 96, "n_traj_choices": (64, 256, 1024, 4096), "n_traj_weights": (0.5, 0.3, 0.15, 0.05),
+             "n_step_choices": (500, 1000), "large_n_traj": (8, 16)}
 SERVE_HBM_BUDGET = 256 * 1024 ** 3
+SERVE_LAUNCH = {2: {"block_threads": 64, "lds_bytes": 4096, "grid_blocks": 0, "use_graph": 1, "flags": 0},
+                3: {"block_threads": 512, "lds_bytes": 54272, "grid_blocks": 0, "use_graph": 1, "flags": 0}}
 
 
 def config1_job() -> JobSpec:
@@ -79,7 +82,8 @@ def config4_jobs(n_traj: int = 256) -> list[JobSpec]:
 
 def serving_stream(n_jobs: int, rate_per_s: float, seed: int = 1, max_l3: int = 96,
                    n_traj_choices=(64, 128, 256), n_step_choices=(500, 1000),
-                   l2_choices=(24, 32, 48, 64, 96), l3_weights=None, large_n_traj=(16, 32)):
+                   l2_choices=(24, 32, 48, 64, 96), l3_weights=None, large_n_traj=(16, 32),
+                   n_traj_weights=None):
     """Poisson arrivals (mean rate_per_s) of jobs of random dimension, size,
     beta, l, N and n_t.  Returns [(arrival_time_s, JobSpec)].
 
@@ -87,8 +91,9 @@ def serving_stream(n_jobs: int, rate_per_s: float, seed: int = 1, max_l3: int = 
     24, 32 at 30 % each and 48, 64, 96 at 5, 3 and 2 %), restricted to
     L <= max_l3.  beta uniform in {0.21, 0.2216546, 0.23}.  n_t from
     n_traj_choices, except 3D lattices of L >= 48 (streamed from HBM), which
-    take n_t from large_n_traj.  2D and on-chip 3D jobs store bit-packed 3D /
-    int8 2D spins; streamed jobs int8."""
+    take n_t from large_n_traj.  n_t is uniform over n_traj_choices, or drawn
+    with n_traj_weights.  2D and on-chip 3D jobs store bit-packed 3D / int8
+    2D spins; streamed jobs int8."""
     rng = np.random.Generator(np.random.PCG64(seed))
     if l3_weights is None:
         l3_weights = {16: 0.30, 24: 0.30, 32: 0.30, 48: 0.05, 64: 0.03, 96: 0.02}
@@ -108,7 +113,12 @@ def serving_stream(n_jobs: int, rate_per_s: float, seed: int = 1, max_l3: int = 
         l = int(rng.integers(0, L))
         n_step = int(rng.choice(n_step_choices))
         streamed = dim == 3 and L >= 48
-        n_traj = int(rng.choice(large_n_traj if streamed else n_traj_choices))
+        if streamed:
+            n_traj = int(rng.choice(large_n_traj))
+        elif n_traj_weights is not None:
+            n_traj = int(rng.choice(n_traj_choices, p=np.asarray(n_traj_weights, dtype=float)))
+        else:
+            n_traj = int(rng.choice(n_traj_choices))
         fmt = EE_SPINS_INT8 if (dim == 2 or streamed) else EE_SPINS_BITPACKED
         out.append((t, JobSpec(dim=dim, lt=L, lx=L, ly=L if dim == 3 else 1, n=2, beta=beta, l=l,
                                n_step=n_step, n_traj=n_traj, seed=1000 + i, spin_format=fmt)))
