@@ -1,4 +1,6 @@
-"""Zero-temperature entropic c-function campaign in 2D (Sec. 4, Table 1).
+"""Physics campaigns of the paper with this build's estimator.
+
+Table 1 (Sec. 4): the zero-temperature entropic c-function in 2D.
 
 For a spatial size L the campaign runs every increment l -> l+1, l = 0..L-1,
 of the 2D Ising model at beta_c on an L_tau = 8L cylinder with n = 2
@@ -18,7 +20,21 @@ Lattices that fit one workgroup's LDS run through the persistent batch;
 larger ones (L >= 128 here) run through the HBM-streaming path, one job
 after another.
 
+Three further checks of the paper (experiment, and its section):
+
+* zero3d (Sec. 5, zero-temperature condition in 3D): every increment of the
+  3D Ising model at beta_c on L_tau x L x L with L_tau = L and L_tau = 4L.  At
+  zero temperature the state is pure, so S_2(L) = sum_l dS_2(l) vanishes and
+  C(x) = -C(1-x); at L_tau = L it does not.
+* dirrev (Sec. 4 and 5, direct and reverse realisations; App. A): every
+  increment estimated from both ends, Delta F_forward = -Delta F_reverse,
+  with chi^2/nu of their sum over all x.
+* proto12 (App. B, protocol 2): every increment in 3D with the ramped row
+  moved at once (protocol 1) and one row at a time (protocol 2), chi^2/nu of
+  their difference over all x.
+
 Usage: python -m paper_2304_03311_amd.campaign --L 32 64 128 --n-traj 1024
+       python -m paper_2304_03311_amd.campaign --experiment zero3d --L 8 16 --out results/zero3d.json
 """
 from __future__ import annotations
 
@@ -80,9 +96,114 @@ def table1_row(L: int, dS: np.ndarray, dS_err: np.ndarray) -> dict:
             "x": x.tolist(), "C": C.tolist(), "C_err": err.tolist()}
 
 
+def run_specs(specs, n_therm: int):
+    """Results of the jobs: one persistent batch for those on chip, the
+    per-job path for the others."""
+    on = [s for s in specs if ee.ee_job_on_chip(s.desc())]
+    off = [s for s in specs if not ee.ee_job_on_chip(s.desc())]
+    res = {}
+    if on:
+        jobs = [ee.Job(s) for s in on]
+        ee.batch_run(jobs, n_therm)
+        for s, j in zip(on, jobs):
+            res[id(s)] = j.estimate()
+            j.close()
+    for s in off:
+        j = ee.Job(s)
+        j.thermalize(n_therm)
+        j.run_protocol()
+        res[id(s)] = j.estimate()
+        j.close()
+    return [res[id(s)] for s in specs]
+
+
+def _increments(dim: int, L: int, lt: int, beta: float, n_traj: int, n_step: int, seed0: int, **kw):
+    return [ee.JobSpec(dim=dim, lt=lt, lx=L, ly=L if dim == 3 else 1, n=2, beta=beta, l=l, n_step=n_step,
+                       n_traj=n_traj, seed=seed0 + l,
+                       spin_format=ee.EE_SPINS_BITPACKED if dim == 3 else ee.EE_SPINS_INT8, **kw)
+            for l in range(L)]
+
+
+def _symmetry(dS, dS_err, L, dim):
+    """S_2(L) with its error, and chi^2 per pair of C(x) + C(1-x) (zero at
+    zero temperature), from the increments."""
+    S, S_err = analysis.renyi_from_increments(dS, dS_err)
+    x, C = analysis.c_function(dS, L, dim=dim)
+    area = 2.0 if dim == 2 else 2.0 * L
+    C_err = ((L / math.pi) * np.sin(math.pi * x)) ** (dim - 1) * np.asarray(dS_err) / area
+    half = len(x) // 2
+    pair = C[:half] + C[::-1][:half]
+    pair_err = np.sqrt(C_err[:half] ** 2 + C_err[::-1][:half] ** 2)
+    return float(S[-1]), float(S_err[-1]), float(np.mean((pair / pair_err) ** 2)), x, C, C_err
+
+
+def zero_temperature(dim: int, L: int, lt_factor: int, n_traj: int, n_step: int, n_therm: int,
+                     beta: float | None = None, seed0: int = 1) -> dict:
+    """Every increment l -> l+1 on an L_tau = lt_factor L lattice: S_2(L) and
+    the symmetry of C(x) (Sec. 5 zero-temperature condition; Sec. 4 in 2D)."""
+    beta = (workloads.BETA_3D if dim == 3 else workloads.BETA_C_2D) if beta is None else beta
+    specs = _increments(dim, L, lt_factor * L, beta, n_traj, n_step, seed0)
+    t0 = time.perf_counter()
+    res = run_specs(specs, n_therm)
+    dt = time.perf_counter() - t0
+    dS = np.array([r.dS for r in res])
+    err = np.array([r.dF_err for r in res])
+    S_L, S_L_err, chi_sym, x, C, C_err = _symmetry(dS, err, L, dim)
+    return {"experiment": "zero-temperature condition", "dim": dim, "L": L, "L_tau": lt_factor * L,
+            "beta": beta, "n_traj": n_traj, "n_step": n_step, "n_therm": n_therm, "S_L": S_L,
+            "S_L_err": S_L_err, "S_L_sigmas": S_L / S_L_err, "chi2_symmetry": chi_sym, "seconds": dt,
+            "dS": dS.tolist(), "dS_err": err.tolist(), "x": x.tolist(), "C": C.tolist(), "C_err": C_err.tolist()}
+
+
+def direct_vs_reverse(dim: int, L: int, lt_factor: int, n_traj: int, n_step: int, n_therm: int,
+                      beta: float | None = None, seed0: int = 1) -> dict:
+    """Every increment from both ends: forward (add column l, A(l) -> A(l+1))
+    and reverse (remove it).  Delta F_f = -Delta F_r (App. A); chi^2/nu of
+    Delta F_f + Delta F_r over all x (Sec. 4 and 5 compare the two
+    realisations the same way)."""
+    beta = (workloads.BETA_3D if dim == 3 else workloads.BETA_C_2D) if beta is None else beta
+    fwd = _increments(dim, L, lt_factor * L, beta, n_traj, n_step, seed0)
+    rev = _increments(dim, L, lt_factor * L, beta, n_traj, n_step, seed0 + 10000, reverse=True)
+    t0 = time.perf_counter()
+    res = run_specs(fwd + rev, n_therm)
+    dt = time.perf_counter() - t0
+    f, r = res[:L], res[L:]
+    d = np.array([a.dF + b.dF for a, b in zip(f, r)])
+    e = np.array([math.hypot(a.dF_err, b.dF_err) for a, b in zip(f, r)])
+    return {"experiment": "direct vs reverse", "dim": dim, "L": L, "L_tau": lt_factor * L, "beta": beta,
+            "n_traj": n_traj, "n_step": n_step, "n_therm": n_therm, "chi2_per_dof": float(np.mean((d / e) ** 2)),
+            "dof": L, "seconds": dt, "dF_forward": [a.dF for a in f], "dF_reverse": [b.dF for b in r],
+            "err_forward": [a.dF_err for a in f], "err_reverse": [b.dF_err for b in r]}
+
+
+def protocol1_vs_2(L: int, lt_factor: int, n_traj: int, n_step: int, n_therm: int, beta: float | None = None,
+                   seed0: int = 1) -> dict:
+    """3D: every increment with the L links of the ramped row moved at once
+    (protocol 1) and one row after the other (protocol 2, App. B); chi^2/nu
+    of the difference over all x.  n_step must be a multiple of L."""
+    beta = workloads.BETA_3D if beta is None else beta
+    p1 = _increments(3, L, lt_factor * L, beta, n_traj, n_step, seed0)
+    p2 = _increments(3, L, lt_factor * L, beta, n_traj, n_step, seed0 + 20000, subsets=True)
+    t0 = time.perf_counter()
+    res = run_specs(p1 + p2, n_therm)
+    dt = time.perf_counter() - t0
+    a, b = res[:L], res[L:]
+    d = np.array([u.dF - v.dF for u, v in zip(a, b)])
+    e = np.array([math.hypot(u.dF_err, v.dF_err) for u, v in zip(a, b)])
+    return {"experiment": "protocol 1 vs protocol 2", "dim": 3, "L": L, "L_tau": lt_factor * L, "beta": beta,
+            "n_traj": n_traj, "n_step": n_step, "n_therm": n_therm, "chi2_per_dof": float(np.mean((d / e) ** 2)),
+            "dof": L, "seconds": dt, "dF_protocol1": [u.dF for u in a], "dF_protocol2": [v.dF for v in b],
+            "err_protocol1": [u.dF_err for u in a], "err_protocol2": [v.dF_err for v in b],
+            "w_var_protocol1": [u.w_var for u in a], "w_var_protocol2": [v.w_var for v in b]}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
+    ap.add_argument("--experiment", default="table1", choices=["table1", "zero3d", "dirrev", "proto12"])
+    ap.add_argument("--dim", type=int, default=2, help="dirrev: lattice dimension")
     ap.add_argument("--L", type=int, nargs="+", default=[32, 64])
+    ap.add_argument("--lt-factor", type=int, nargs="+", default=None,
+                    help="L_tau / L (table1: 8; zero3d: 1 4; dirrev: 8 in 2D, 4 in 3D; proto12: 4)")
     ap.add_argument("--n-traj", type=int, default=1024)
     ap.add_argument("--n-step", type=int, default=1000)
     ap.add_argument("--n-therm", type=int, default=1000)
@@ -92,13 +213,25 @@ def main(argv=None) -> int:
     torch.cuda.set_device(0)
     rows = []
     for L in args.L:
-        specs, res, dt, on_chip = run_increments(L, args.n_traj, args.n_step, args.n_therm)
-        row = table1_row(L, np.array([r.dS for r in res]), np.array([r.dF_err for r in res]))
-        att = sum(r.attempts for r in res)
-        row.update(n_traj=args.n_traj, n_step=args.n_step, n_therm=args.n_therm, seconds=dt,
-                   attempts_per_ns=att / (dt * 1e9), path="persistent batch" if on_chip else "HBM streaming")
-        rows.append(row)
-        brief = {k: v for k, v in row.items() if k not in ("x", "C", "C_err")}
+        if args.experiment == "table1":
+            specs, res, dt, on_chip = run_increments(L, args.n_traj, args.n_step, args.n_therm)
+            row = table1_row(L, np.array([r.dS for r in res]), np.array([r.dF_err for r in res]))
+            att = sum(r.attempts for r in res)
+            row.update(n_traj=args.n_traj, n_step=args.n_step, n_therm=args.n_therm, seconds=dt,
+                       attempts_per_ns=att / (dt * 1e9), path="persistent batch" if on_chip else "HBM streaming")
+            rows.append(row)
+            continue
+        if args.experiment == "zero3d":
+            for f in (args.lt_factor or [1, 4]):
+                rows.append(zero_temperature(3, L, f, args.n_traj, args.n_step, args.n_therm))
+        elif args.experiment == "dirrev":
+            f = (args.lt_factor or [8 if args.dim == 2 else 4])[0]
+            rows.append(direct_vs_reverse(args.dim, L, f, args.n_traj, args.n_step, args.n_therm))
+        else:
+            f = (args.lt_factor or [4])[0]
+            rows.append(protocol1_vs_2(L, f, args.n_traj, args.n_step, args.n_therm))
+    for row in rows:
+        brief = {k: v for k, v in row.items() if not isinstance(v, list)}
         print(json.dumps(brief), flush=True)
     if args.out:
         with open(args.out, "w") as f:

@@ -2,7 +2,10 @@
 
 * Delta F of every increment l -> l+1 on a 2D 16x4 and a 3D 4x2x2 lattice
   against the exact transfer-matrix value -log Z_n(l+1)/Z_n(l) (Sec. 2, 3);
-* the direct/reverse equality <e^-W>_dir = <e^-W>_rev^-1 (App. A);
+* the direct/reverse equality <e^-W>_dir = <e^-W>_rev^-1 (App. A), at one
+  increment and over every increment of a 3D lattice (Sec. 5);
+* protocols 1 and 2 (App. B) over every increment of a 3D lattice;
+* the 3D zero-temperature condition of Sec. 5 (L_tau = 4L against L_tau = L);
 * the 2D c-function at L_tau = 8L against the CFT form with the finite-size
   fit of Sec. 4.
 """
@@ -132,3 +135,41 @@ def test_2d_c_function_zero_temperature_vs_cft_and_table1():
     assert abs(row["k"] - ref["k"]) < 3.0 * math.hypot(row["k_err"], ref["k_err"])
     assert row["chi2_fit"] < 2.5
     assert row["chi2_symmetry"] < 2.5
+
+
+def test_3d_zero_temperature_condition():
+    """Sec. 5: with L_tau = 4L the 3D system is at zero temperature: the state
+    of the whole space is pure, so S_2(L) = sum_l dS_2(l) vanishes and
+    C(x) = -C(1-x).  With L_tau = L it is a thermal state and neither holds.
+    3D Ising at beta_c, L = 16, every increment, 1024 trajectories."""
+    from paper_2304_03311_amd import campaign
+    hot = campaign.zero_temperature(3, 16, 1, 1024, 1000, 10000)
+    cold = campaign.zero_temperature(3, 16, 4, 1024, 1000, 10000)
+    for r in (hot, cold):
+        print(f"[gpu] 3D L=16 L_tau={r['L_tau']}: S_2(L) = {r['S_L']:.4f} +- {r['S_L_err']:.4f}, "
+              f"C(x)+C(1-x) chi2/pair = {r['chi2_symmetry']:.2f}", file=sys.stderr, flush=True)
+    assert hot["S_L"] > 10 * hot["S_L_err"] and hot["chi2_symmetry"] > 10
+    assert abs(cold["S_L"]) < 3 * cold["S_L_err"] and cold["chi2_symmetry"] < 2.5
+
+
+def test_direct_and_reverse_agree_over_all_x_3d():
+    """Sec. 5 compares the direct and reverse realisations over every x
+    (reduced chi^2 0.70 in 3D); here 3D L = 16, L_tau = 4L, 16 increments."""
+    import json
+    import os
+    from paper_2304_03311_amd import campaign
+    paper = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    r = campaign.direct_vs_reverse(3, 16, 4, 1024, 1000, 10000)
+    print(f"[gpu] direct vs reverse 3D L=16: chi2/nu = {r['chi2_per_dof']:.2f} over {r['dof']} "
+          f"(paper: {paper['direct_vs_reverse_chi2_dof']['d3']})", file=sys.stderr, flush=True)
+    assert r["chi2_per_dof"] < 2.5  # nu = 16: exceeded with probability < 0.1%
+
+
+def test_protocol1_and_protocol2_agree_over_all_x():
+    """App. B: moving the ramped row's links one row at a time (protocol 2)
+    estimates the same increments as moving them together (protocol 1)."""
+    from paper_2304_03311_amd import campaign
+    r = campaign.protocol1_vs_2(16, 4, 1024, 1600, 10000)
+    print(f"[gpu] protocol 1 vs 2, 3D L=16: chi2/nu = {r['chi2_per_dof']:.2f} over {r['dof']}",
+          file=sys.stderr, flush=True)
+    assert r["chi2_per_dof"] < 2.5
