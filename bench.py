@@ -36,7 +36,8 @@ BYTES_PER_ATTEMPT = 2.0
 # site per sweep.
 STREAM_BYTES_PER_ATTEMPT = 3.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_2d64_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_03311_amd", "csrc", f) for f in ("ee_kernels.hip", "ee_internal.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_03311_amd", "csrc", f)
+                  for f in ("ee_kernels.hip", "ee_internal.hpp", "ee_dd.hpp")]
 
 
 def kernel_hash() -> str:
