@@ -910,6 +910,22 @@ __device__ long long block_reduce_ll(long long v, long long* sh, Op op) {
   return r;
 }
 
+// Visit load(0), load(1), ... load(n-1) in order with add(), loading
+// kEstGroup values ahead of their adds.
+constexpr int kEstGroup = 16;
+template <typename Load, typename Add>
+__device__ __forceinline__ void for_groups(int n, Load load, Add add) {
+  int j = 0;
+  for (; j + kEstGroup <= n; j += kEstGroup) {
+    double v[kEstGroup];
+#pragma unroll
+    for (int k = 0; k < kEstGroup; ++k) v[k] = load(j + k);
+#pragma unroll
+    for (int k = 0; k < kEstGroup; ++k) add(v[k]);
+  }
+  for (; j < n; ++j) add(load(j));
+}
+
 __global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* const* jobtab) {
   __shared__ double tile[kEstTile];
   __shared__ long long shl[kEstWaves];
@@ -935,24 +951,26 @@ __global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* con
   for (int i = tid; i < n; i += kEstThreads) e[i] = ee::dd::exp_cr((beta * (double)(I[i] - imax)) / N);
   __syncthreads();
 
-  // The sums in ascending j, each by one lane of its own wave.
+  // The sums in ascending j, each by one lane of its own wave.  The loads of
+  // a group of kEstGroup terms are issued before its adds, which stay in
+  // order: one memory latency per group instead of one per term.
   if (tid == 0) {
     double s = 0.0;
-    for (int j = 0; j < n; ++j) s += e[j];
+    for_groups(n, [&](int j) { return e[j]; }, [&](double v) { s += v; });
     shd[0] = s;
   } else if (tid == 64) {
     double s2 = 0.0;
-    for (int j = 0; j < n; ++j) s2 += e[j] * e[j];
+    for_groups(n, [&](int j) { return e[j]; }, [&](double v) { s2 += v * v; });
     shd[1] = s2;
   } else if (tid == 128) {
     double wm = 0.0;
-    for (int j = 0; j < n; ++j) wm += -(beta / N) * (double)I[j];
+    for_groups(n, [&](int j) { return (double)I[j]; }, [&](double v) { wm += -(beta / N) * v; });
     wm /= n;
     double wv = 0.0;
-    for (int j = 0; j < n; ++j) {
-      const double d = -(beta / N) * (double)I[j] - wm;
+    for_groups(n, [&](int j) { return (double)I[j]; }, [&](double v) {
+      const double d = -(beta / N) * v - wm;
       wv += d * d;
-    }
+    });
     wv /= n;
     shd[2] = wm;
     shd[3] = wv;
@@ -1005,10 +1023,10 @@ __global__ void __launch_bounds__(kEstThreads) estimate_kernel(const JobDev* con
     double err = __builtin_nan("");
     if (n >= 2) {
       double mean = 0.0;
-      for (int i = 0; i < n; ++i) mean += loo[i];
+      for_groups(n, [&](int i) { return loo[i]; }, [&](double v) { mean += v; });
       mean /= n;
       double acc = 0.0;
-      for (int i = 0; i < n; ++i) acc += (loo[i] - mean) * (loo[i] - mean);
+      for_groups(n, [&](int i) { return loo[i]; }, [&](double v) { acc += (v - mean) * (v - mean); });
       err = sqrt((double)(n - 1) / (double)n * acc);
     }
     res->dF = dF;

@@ -43,7 +43,7 @@ BENCH_LAUNCH = {"block_threads": 64, "lds_bytes": 8192, "grid_blocks": 0, "use_g
 # chunk launches by dimension: 2D lattices in one-wave workgroups of up to
 # 4 KiB (the tuner's shapes for the 2D sets), 3D in 512-thread workgroups
 # (the tuner's shape for the 3D-heavy 24-job set)
-SERVE_MIX = {"max_l3": 96, "n_traj_choices": (64, 256, 1024, 4096), "n_traj_weights": (0.5, 0.3, 0.15, 0.05),
+SERVE_MIX = {"max_l3": 96, "n_traj_choices": (64, 256, 1024, 4096), "n_traj_weights": (0.54, 0.3, 0.125, 0.035),
              "n_step_choices": (500, 1000), "large_n_traj": (8, 16)}
 SERVE_HBM_BUDGET = 256 * 1024 ** 3
 SERVE_LAUNCH = {2: {"block_threads": 64, "lds_bytes": 4096, "grid_blocks": 0, "use_graph": 1, "flags": 0},
