@@ -183,14 +183,19 @@ def configs_run() -> dict:
     return out
 
 
-def streaming_run() -> dict:
+def streaming_run(n_traj: int = 32, march: bool = False) -> dict:
     """Throughput of the HBM-streaming path on the largest serving shape
-    (3D 96^3, n = 2, 32 trajectories, N = 100 after 10 thermalisation sweeps)."""
+    (3D 96^3, n = 2, N = 100 after 10 thermalisation sweeps): 32
+    trajectories on the two-pass kernel (3 B per attempt), or 256 on the
+    plane-marching kernel (each plane read and written once per sweep,
+    2 B per attempt)."""
     import torch
     from paper_2304_03311_amd import ee, workloads
-    spec = ee.JobSpec(dim=3, lt=96, lx=96, ly=96, n=2, beta=workloads.BETA_3D, l=40, n_step=100, n_traj=32,
+    spec = ee.JobSpec(dim=3, lt=96, lx=96, ly=96, n=2, beta=workloads.BETA_3D, l=40, n_step=100, n_traj=n_traj,
                       seed=5)
+    flags = ee.EE_LAUNCH_MARCH if march else ee.EE_LAUNCH_TWO_PASS
     job = ee.Job(spec)
+    job.set_launch({"flags": flags})
     job.thermalize(2)  # warm-up launches
     torch.cuda.synchronize()
     job.reset()
@@ -200,11 +205,12 @@ def streaming_run() -> dict:
     r = job.estimate()
     dt = time.perf_counter() - t0
     job.close()
-    return {"workload": "3D 96^3, n=2, n_t=32, N=100, N_therm=10, int8 in HBM", "attempts_per_ns": r.attempts / (dt * 1e9),
-            "ms": dt * 1e3, "launches": 2 * 110 + 3,
-            "algorithmic_bytes_per_attempt": STREAM_BYTES_PER_ATTEMPT,
-            "hbm_GBps_algorithmic": STREAM_BYTES_PER_ATTEMPT * r.attempts / dt / 1e9,
-            "hbm_frac": hbm_frac(r.attempts, dt, STREAM_BYTES_PER_ATTEMPT)}
+    bpa = BYTES_PER_ATTEMPT if march else STREAM_BYTES_PER_ATTEMPT
+    kernel = "march_kernel + march_fixup_kernel" if march else "stream_sweep_kernel (one launch per colour)"
+    return {"workload": f"3D 96^3, n=2, n_t={n_traj}, N=100, N_therm=10, int8 in HBM", "kernel": kernel,
+            "attempts_per_ns": r.attempts / (dt * 1e9), "ms": dt * 1e3, "launches": 2 * 110 + 3,
+            "algorithmic_bytes_per_attempt": bpa, "hbm_GBps_algorithmic": bpa * r.attempts / dt / 1e9,
+            "hbm_frac": hbm_frac(r.attempts, dt, bpa)}
 
 
 def main() -> int:
@@ -245,7 +251,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.stream_only:
-        print(json.dumps({"streaming_path": streaming_run()}), flush=True)
+        print(json.dumps({"streaming_path": streaming_run(),
+                          "streaming_march": streaming_run(256, march=True)}), flush=True)
         return 0
     if args.serve_only:
         print(json.dumps({"serving": serving_run(args.serve_jobs)}), flush=True)
@@ -337,6 +344,7 @@ def main() -> int:
     if not args.no_serve:
         out["serving"] = serving_run(args.serve_jobs)
         out["streaming_path"] = streaming_run()
+        out["streaming_march"] = streaming_run(256, march=True)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     for j in jobs:

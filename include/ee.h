@@ -214,6 +214,21 @@ typedef struct {
  * spins stay in HBM and every half-sweep is one launch over all
  * trajectories, with bit-identical results. */
 #define EE_LAUNCH_STREAMING 1u
+/* Kernel of the HBM-streaming path (either flag implies EE_LAUNCH_STREAMING).
+ * Streamed jobs run the two-pass kernel (one launch per colour: 3 B of HBM
+ * traffic per site and sweep) unless EE_LAUNCH_MARCH selects the
+ * plane-marching kernel: each workgroup marches the t-planes of one segment
+ * of one replica of one trajectory through a five-slot LDS ring (a plane:
+ * both colours, all y, 2 ly G words), updating colour 0 of plane p and
+ * colour 1 of plane p-1 at each step, so each plane is read and written once
+ * per sweep (2 B per site); colour 1 of each segment's first and last plane
+ * (planes t = 0 and 1 among them) follows in a second launch.  grid_blocks
+ * > 0 then sets the segments per trajectory (at most lt/2), else the
+ * runtime picks them; ee_job_set_launch returns EE_EUNSUPPORTED if the ring
+ * does not fit LDS.  EE_LAUNCH_TWO_PASS names the default explicitly.
+ * Results are bit-identical either way. */
+#define EE_LAUNCH_MARCH 2u
+#define EE_LAUNCH_TWO_PASS 4u
 /* ee_batch_run with an explicit launch shape (NULL = defaults). */
 ee_status ee_batch_run_cfg(ee_job* const* jobs, int32_t count, int32_t n_therm,
                            const ee_launch_cfg* cfg, void* hip_stream);

@@ -99,6 +99,12 @@ int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c
                              int work, void* stream);
 int ee_k_launch_stream_init(const ee::JobDev* job, int n_traj, int lanes, void* stream);
 int ee_k_launch_zero_work(const ee::JobDev* job, int n_traj, void* stream);
+// Plane-marching kernel: LDS bytes of a workgroup whose plane (one
+// replica, both colours) has plane_words words; one sweep (main pass over
+// n_traj * n_replicas * nseg workgroups, then the fix-up pass).
+int ee_k_march_lds_bytes(int plane_words);
+int ee_k_launch_march(const ee::JobDev* job, int n_traj, int n_replicas, int nseg, int block, int plane_words,
+                      uint32_t g, int pos, int dpos, int work, void* stream);
 size_t ee_k_scratch_bytes();
 int ee_k_scratch_ptr(void** out);
 }

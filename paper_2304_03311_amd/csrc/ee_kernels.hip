@@ -212,7 +212,9 @@ __device__ __forceinline__ uint32_t half16(uint32_t word, int hi) { return hi ? 
 // 2 takes the next one).  PAR: the row's x parity p = (c + t + y) & 1 when
 // the caller knows it at compile time, else -1.  CUT: the code for rows next
 // to the cut (t = 0, 1) is compiled in; without it the row must have t > 1.
-template <int DIM, bool FULL, int W, int PAR, bool CUT>
+// XG: the glued partner row is at Lo + og_in (a layout other than the
+// colour-plane storage order), with the parity known only at run time.
+template <int DIM, bool FULL, int W, int PAR, bool CUT, bool XG = false>
 __device__ __forceinline__ void row_update(const JP& P, const int w, const int wl, const int wr,
                                            uint32_t* __restrict__ Lc, const uint32_t* __restrict__ Lo,
                                            const uint32_t* __restrict__ thr, const int c, const uint32_t g,
@@ -273,7 +275,7 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   // caller knows the parity at compile time)
   const auto gmq = [&](int q) { return (PAR >= 0) ? gm_in[q] : glued_mask(P.l - p - 8 * (w + q)); };
   if (cutrow) {
-    const int og = (PAR >= 0) ? og_in : glued_row(P, r, t, y) * G + w;
+    const int og = (PAR >= 0 || XG) ? og_in : glued_row(P, r, t, y) * G + w;
     ld_words<W>(Lo + og, Tgl);
 #pragma unroll
     for (int q = 0; q < W; ++q) {
@@ -858,6 +860,365 @@ stream_sweep_kernel(const JobDev* J, int lanes, int c, uint32_t g, int pos, int 
   stream_body(J, lanes, c, g, pos, dpos, work);
 }
 
+// ---------------------------------------------------------------------------
+// Plane-marching streaming path: lattices larger than one workgroup's LDS,
+// jobs with enough trajectories to fill the GPU with long marches.  One
+// sweep is one launch of march_kernel and one of march_fixup_kernel.
+//
+// A plane is every site of one replica with one t (all y, both colours).
+// A sweep updates colour 0 everywhere with colour 1 unchanged, then colour
+// 1 with colour 0 new (the oracle's order; sites of one colour are
+// independent).  Workgroup (j, r, s) marches the planes of segment s of
+// replica r of trajectory j through a ring of kMarchSlots plane slots in
+// LDS: at step p it updates colour 0 of plane p (colour 1 of planes p-1, p,
+// p+1 still old) and then colour 1 of plane p-1 (colour 0 of planes p-2,
+// p-1, p already new), while plane p+2 is loaded and plane p-2, final,
+// written back.  Each plane is read and written once per sweep, 2 B per
+// site.  Colour 1 of a segment's first and last plane needs colour 0 of the
+// neighbouring segments' planes, so it is left to march_fixup_kernel; the
+// main pass only reads colour 1 of the neighbouring segments' boundary
+// planes, which nobody writes during it.  Segments cover the unwrapped
+// planes [1, lt + 1) (plane lt is t = 0), so planes t = 1 and t = 0, the
+// rows next to the cut, are always boundary planes: the main pass updates
+// only their colour 0, whose glued partners (colour 1 of replica r +- 1 in
+// plane 1 - t) it reads from HBM, unchanged by the main pass.
+// ---------------------------------------------------------------------------
+constexpr int kMarchSlots = 5;
+__device__ __forceinline__ void segment_bounds(int lt, int nseg, int s, int& t0, int& t1) {
+  t0 = 1 + (int)((int64_t)lt * s / nseg);
+  t1 = 1 + (int)((int64_t)lt * (s + 1) / nseg);
+}
+
+// Plane transfers between replica r of the trajectory in HBM (colour-plane
+// storage) and a ring slot ([colour][y][word], the rows of the plane in
+// storage order, so that slot unit i is simply the i-th unit of the slot).
+// A unit is four words when the row length G is a multiple of 4, else one
+// word; GV units per row.  The HBM side goes through global-address-space
+// pointers: flat accesses would also count against the LDS wait counter, so
+// that every LDS wait of the compute phases would wait for the transfers
+// in flight.  A 16-byte unit is a native four-word vector.
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+template <typename V>
+using gptr = __attribute__((address_space(1))) V*;
+
+// HBM word offset, at t = 0, of unit u of a plane of replica r.
+__device__ __forceinline__ int unit_offset(const JP& P, int r, int u, int GV, int uw) {
+  const int q = u / GV, wv = u - q * GV;
+  const int c = q / P.ly, y = q - c * P.ly;
+  return ((c * P.n + r) * P.R + y) * P.G + uw * wv;
+}
+
+template <bool TO_LDS, typename V>
+__device__ __forceinline__ void plane_copy_v(const JP& P, uint32_t* traj, uint32_t* slot, int r, int t, int i_lo,
+                                             int i_hi, int GV) {
+  constexpr int UW = sizeof(V) / 4;
+  V* sv = reinterpret_cast<V*>(slot);
+  const gptr<uint32_t> base = (gptr<uint32_t>)(traj + t * P.ly * P.G);
+  for (int i = i_lo + (int)threadIdx.x; i < i_hi; i += blockDim.x) {
+    const gptr<V> g = (gptr<V>)(base + unit_offset(P, r, i, GV, UW));
+    if (TO_LDS) sv[i] = *g;
+    else *g = sv[i];
+  }
+}
+
+// Copy colours [c_lo, c_hi) of plane t (synchronously: each unit's load or
+// store is followed by its use).
+template <bool TO_LDS>
+__device__ __forceinline__ void plane_copy(const JP& P, uint32_t* traj, uint32_t* slot, int r, int t, int c_lo,
+                                           int c_hi) {
+  if ((P.G & 3) == 0) {
+    const int GV = P.G >> 2;
+    plane_copy_v<TO_LDS, v4u>(P, traj, slot, r, t, c_lo * P.ly * GV, c_hi * P.ly * GV, GV);
+  } else {
+    plane_copy_v<TO_LDS, uint32_t>(P, traj, slot, r, t, c_lo * P.ly * P.G, c_hi * P.ly * P.G, P.G);
+  }
+}
+
+// This thread's share of the plane transfers: 16-byte units u0 + k T
+// (k < 4) of a plane, with their HBM word offsets at t = 0 (the units of
+// plane t sit at the same offsets plus t ly G words), computed once per
+// launch.  A load is split in two: xfer_fetch() issues the loads into
+// registers, xfer_put() writes them to the slot; between the two the loads
+// are in flight while the workgroup computes.  Units from 4 T on, and
+// planes whose rows are not a multiple of four words, are copied at once.
+struct Xfer {
+  int o0, o1, o2, o3;  // HBM word offsets (t = 0) of units u0 + k T
+  int u0, T, U, U0;    // first unit, stride, units per plane, units of colour 0
+  int GV, tw, r;       // units per row, HBM words per plane step (ly G), replica
+  bool vec;            // rows of a multiple of four words
+};
+
+__device__ __forceinline__ Xfer make_xfer(const JP& P, int r) {
+  Xfer X;
+  X.vec = (P.G & 3) == 0;
+  X.GV = P.G >> 2;
+  X.U = 2 * P.ly * X.GV;
+  X.U0 = P.ly * X.GV;
+  X.T = blockDim.x;
+  X.u0 = threadIdx.x;
+  X.tw = P.ly * P.G;
+  X.r = r;
+  const auto off = [&](int u) { return (X.vec && u < X.U) ? unit_offset(P, r, u, X.GV, 4) : 0; };
+  X.o0 = off(X.u0);
+  X.o1 = off(X.u0 + X.T);
+  X.o2 = off(X.u0 + 2 * X.T);
+  X.o3 = off(X.u0 + 3 * X.T);
+  return X;
+}
+
+// Issue the loads of colours [c_lo, 2) of plane t.
+__device__ __forceinline__ void xfer_fetch(const Xfer& X, const JP& P, uint32_t* traj, uint32_t* slot, int t,
+                                           int c_lo, v4u& v0, v4u& v1, v4u& v2, v4u& v3) {
+  if (!X.vec) {
+    plane_copy<true>(P, traj, slot, X.r, t, c_lo, 2);
+    return;
+  }
+  const int lo = c_lo * X.U0;
+  const gptr<uint32_t> base = (gptr<uint32_t>)(traj + t * X.tw);
+  const auto ld = [&](int k, int o, v4u& v) {
+    const int u = X.u0 + k * X.T;
+    if (u >= lo && u < X.U) v = *(gptr<v4u>)(base + o);
+  };
+  ld(0, X.o0, v0);
+  ld(1, X.o1, v1);
+  ld(2, X.o2, v2);
+  ld(3, X.o3, v3);
+  if (4 * X.T < X.U) plane_copy_v<true, v4u>(P, traj, slot, X.r, t, max(lo, 4 * X.T), X.U, X.GV);
+}
+
+__device__ __forceinline__ void xfer_put(const Xfer& X, uint32_t* slot, int c_lo, const v4u& v0, const v4u& v1,
+                                         const v4u& v2, const v4u& v3) {
+  if (!X.vec) return;
+  const int lo = c_lo * X.U0;
+  v4u* sv = reinterpret_cast<v4u*>(slot);
+  const auto st = [&](int k, const v4u& v) {
+    const int u = X.u0 + k * X.T;
+    if (u >= lo && u < X.U) sv[u] = v;
+  };
+  st(0, v0);
+  st(1, v1);
+  st(2, v2);
+  st(3, v3);
+}
+
+// Write colours [0, c_hi) of plane t back to HBM.
+__device__ __forceinline__ void xfer_store(const Xfer& X, const JP& P, uint32_t* traj, uint32_t* slot, int t,
+                                           int c_hi) {
+  if (!X.vec) {
+    plane_copy<false>(P, traj, slot, X.r, t, 0, c_hi);
+    return;
+  }
+  const int hi = c_hi * X.U0;
+  const gptr<uint32_t> base = (gptr<uint32_t>)(traj + t * X.tw);
+  const v4u* sv = reinterpret_cast<const v4u*>(slot);
+  const auto st = [&](int k, int o) {
+    const int u = X.u0 + k * X.T;
+    if (u < hi) *(gptr<v4u>)(base + o) = sv[u];
+  };
+  st(0, X.o0);
+  st(1, X.o1);
+  st(2, X.o2);
+  st(3, X.o3);
+  if (4 * X.T < hi) plane_copy_v<false, v4u>(P, traj, slot, X.r, t, 4 * X.T, hi, X.GV);
+}
+
+// A row of a plane's colour: y and first word w.
+struct RowDesc {
+  int y, w;
+};
+
+__device__ __forceinline__ RowDesc row_desc(int it, int GW, int W) {
+  RowDesc d;
+  d.y = it / GW;
+  d.w = (it - d.y * GW) * W;
+  return d;
+}
+
+// Colour c of plane t of replica r (unwrapped plane index p: slots of p-1,
+// p, p+1 are sm, s0, sp) from the ring; PW words per slot.  d0: this
+// thread's first row (the same in every plane).  Rows next to the cut
+// (t <= 1) come here with c = 0 only.
+template <int DIM, bool FULL, int W>
+__device__ __forceinline__ void march_colour(const JP& P, uint32_t* win, uint32_t* traj, int PW, int sm, int s0,
+                                             int sp, int c, int r, int t, const uint32_t* thr, uint32_t g,
+                                             uint32_t j, int pos, int dpos, bool work, int& dI, const RowDesc& d0) {
+  const int G = P.G, GW = G / W, ly = P.ly;
+  uint32_t* own = win + s0 * PW + c * ly * G;
+  const uint32_t* oth = win + s0 * PW + (c ^ 1) * ly * G;
+  const int tmo = (sm - s0) * PW, tpo = (sp - s0) * PW;
+  const uint32_t c3 = (1u << 28) | ((uint32_t)r << 1) | (uint32_t)c;
+  const auto rows = [&](auto cut) {
+    constexpr bool CUT = decltype(cut)::value;
+    // glued partners: colour 1 of replica r+1 in plane 1 (t = 0) or of
+    // replica r-1 in plane 0 (t = 1), in HBM
+    const int rgl = (t == 0) ? ((r + 1 == P.n) ? 0 : r + 1) : ((r == 0) ? P.n - 1 : r - 1);
+    const int ogl = ((P.n + rgl) * P.R + (1 - t) * ly) * G;
+    RowDesc d = d0;
+    for (int it = threadIdx.x; it < ly * GW;) {
+      const int y = d.y, w = d.w;
+      const int wl = (w == 0) ? G - 1 : w - 1, wr = (w + W == G) ? 0 : w + W;
+      const int ymo = (y == 0) ? (ly - 1) * G : -G, ypo = (y == ly - 1) ? -(ly - 1) * G : G;
+      const uint32_t c0 = (uint32_t)((t * ly + y) * P.G8 + (w >> 1));
+      row_update<DIM, FULL, W, -1, CUT, true>(P, w, wl, wr, own, traj, thr, c, g, j, pos, dpos, work, dI, r, t, y,
+                                              own + y * G + w, oth + y * G + w, tmo, tpo, ymo, ypo, c0, c3,
+                                              CUT ? ogl + y * G + w : 0);
+      it += blockDim.x;
+      if (it < ly * GW) d = row_desc(it, GW, W);
+    }
+  };
+  if (t <= 1) rows(std::true_type{});
+  else rows(std::false_type{});
+}
+
+template <int DIM, bool FULL, int W>
+__device__ __forceinline__ void march_segment(const JP& P, uint32_t* win, const uint32_t* thr, int nseg, uint32_t g,
+                                              int pos, int dpos, bool work) {
+  int jj, rs;
+  xcd_block(P.n * nseg, (int)gridDim.x, jj, rs);
+  const int r = rs / nseg, seg = rs - r * nseg;
+  const uint32_t j = (uint32_t)jj;
+  uint32_t* traj = P.spins + (size_t)j * P.traj_words;
+  const int PW = 2 * P.ly * P.G;
+  int t0, t1;
+  segment_bounds(P.lt, nseg, seg, t0, t1);
+  // ring of kMarchSlots slots: plane p in slot (p - t0 + 1) mod kMarchSlots
+  const auto slot = [&](int p) { return (p - t0 + 1) % kMarchSlots; };
+  const auto phys = [&](int p) { return (p >= P.lt) ? p - P.lt : p; };  // 0 <= p < 2 lt
+  const Xfer X = make_xfer(P, r);
+  const RowDesc d0 = row_desc(threadIdx.x, P.G / W, W);
+  int dI = 0;
+  v4u v0 = {}, v1 = {}, v2 = {}, v3 = {};
+  // planes t0-1 .. t0+1; a neighbouring segment's boundary plane
+  // contributes only its colour 1
+  for (int p = t0 - 1; p <= t0 + 1; ++p) {
+    const int c_lo = (p < t0 || p >= t1) ? 1 : 0;
+    xfer_fetch(X, P, traj, win + slot(p) * PW, phys(p), c_lo, v0, v1, v2, v3);
+    xfer_put(X, win + slot(p) * PW, c_lo, v0, v1, v2, v3);
+  }
+  __syncthreads();
+  for (int p = t0; p < t1; ++p) {
+    // step p: colour 0 of plane p (planes p-1 .. p+1 in the ring), then
+    // colour 1 of plane p-1 (planes p-2 .. p).  Meanwhile plane p+2 is
+    // fetched (into registers, then into its slot, free since plane p-3
+    // was written back) and the final plane p-2 is written back.
+    const bool fetch = p + 2 <= t1;
+    const int c_lo = (p + 2 == t1) ? 1 : 0;
+    if (fetch) xfer_fetch(X, P, traj, win + slot(p + 2) * PW, phys(p + 2), c_lo, v0, v1, v2, v3);
+    march_colour<DIM, FULL, W>(P, win, traj, PW, slot(p - 1), slot(p), slot(p + 1), 0, r, phys(p), thr, g, j, pos,
+                               dpos, work, dI, d0);
+    __syncthreads();
+    // plane p-2 is final (colour 1 of the segment's first plane waits for
+    // the fix-up pass)
+    if (p - 2 >= t0) xfer_store(X, P, traj, win + slot(p - 2) * PW, phys(p - 2), (p - 2 > t0) ? 2 : 1);
+    if (p - 1 >= t0 + 1)
+      march_colour<DIM, FULL, W>(P, win, traj, PW, slot(p - 2), slot(p - 1), slot(p), 1, r, phys(p - 1), thr, g, j,
+                                 pos, dpos, false, dI, d0);
+    if (fetch) xfer_put(X, win + slot(p + 2) * PW, c_lo, v0, v1, v2, v3);
+    __syncthreads();
+  }
+  if (t1 - 2 >= t0) xfer_store(X, P, traj, win + slot(t1 - 2) * PW, phys(t1 - 2), (t1 - 2 > t0) ? 2 : 1);
+  xfer_store(X, P, traj, win + slot(t1 - 1) * PW, phys(t1 - 1), 1);
+  if (dI != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.work[j]), (unsigned long long)(long long)dI);
+}
+
+// Colour 1 of each segment's first and last plane, every replica, from HBM
+// (block: one plane of one segment of one trajectory).
+template <int DIM, bool FULL, int W>
+__device__ __forceinline__ void fixup_plane(const JP& P, const uint32_t* thr, int nseg, uint32_t g, int pos,
+                                            int dpos) {
+  const int b = blockIdx.x;
+  const int jj = b / (2 * nseg), rem = b - jj * 2 * nseg, seg = rem >> 1, last = rem & 1;
+  int t0, t1;
+  segment_bounds(P.lt, nseg, seg, t0, t1);
+  if (last && t1 - 1 == t0) return;  // a one-plane segment has one boundary plane
+  const int t = (last ? t1 - 1 : t0) % P.lt;
+  const uint32_t j = (uint32_t)jj;
+  uint32_t* traj = P.spins + (size_t)j * P.traj_words;
+  const int G = P.G, GW = G / W, ly = P.ly, R = P.R;
+  uint32_t* Lc = traj + P.n * R * G;  // colour 1
+  const uint32_t* Lo = traj;          // colour 0
+  const int LyG = ly * G, ltLyG = P.lt * LyG;
+  const int tpo = LyG - ((t == P.lt - 1) ? ltLyG : 0);
+  const int tmo = -LyG + ((t == 0) ? ltLyG : 0);
+  int dI = 0;
+  const auto rows = [&](auto cut) {
+    constexpr bool CUT = decltype(cut)::value;
+    for (int it = threadIdx.x; it < P.n * ly * GW; it += blockDim.x) {
+      const int rr = it / GW, w = (it - rr * GW) * W;
+      const int r = rr / ly, y = rr - r * ly;
+      const int wl = (w == 0) ? G - 1 : w - 1, wr = (w + W == G) ? 0 : w + W;
+      const int ymo = (y == 0) ? (ly - 1) * G : -G, ypo = (y == ly - 1) ? -(ly - 1) * G : G;
+      const int rowbase = (r * R + t * ly + y) * G;
+      const uint32_t c0 = (uint32_t)((t * ly + y) * P.G8 + (w >> 1));
+      const uint32_t c3 = (1u << 28) | ((uint32_t)r << 1) | 1u;
+      row_update<DIM, FULL, W, -1, CUT>(P, w, wl, wr, Lc, Lo, thr, 1, g, j, pos, dpos, false, dI, r, t, y,
+                                        Lc + rowbase + w, Lo + rowbase + w, tmo, tpo, ymo, ypo, c0, c3);
+    }
+  };
+  if (t <= 1) rows(std::true_type{});
+  else rows(std::false_type{});
+}
+
+// Words per lane of the marching kernels: as the on-chip kernel chooses for
+// a workgroup of blockDim lanes per plane.
+template <bool MAIN>
+__device__ __forceinline__ void march_body(const JobDev* J, int nseg, uint32_t g, int pos, int dpos, int work) {
+  extern __shared__ __align__(16) uint32_t march_lds[];
+  const JP P = load_jp(J);
+  const int dim = uni(J->dim);
+  const int PW = 2 * P.ly * P.G;
+  uint32_t* thr = MAIN ? march_lds + kMarchSlots * PW : march_lds;  // after the ring (main pass) or alone (fix-up)
+  if (threadIdx.x < 8)
+    thr[threadIdx.x] = (threadIdx.x == 0) ? P.thr0 : (threadIdx.x == 1) ? P.thr1
+                     : (threadIdx.x == 2 && dim == 3) ? P.thr2 : 0xFFFFFFFFu;
+  __syncthreads();
+  const bool full = (P.H & 3) == 0;
+  const bool w = work != 0;
+  const auto go = [&](auto dimc, auto fullc, auto wc) {
+    constexpr int D = decltype(dimc)::value;
+    constexpr bool F = decltype(fullc)::value;
+    constexpr int WW = decltype(wc)::value;
+    if (MAIN) march_segment<D, F, WW>(P, march_lds, thr, nseg, g, pos, dpos, w);
+    else fixup_plane<D, F, WW>(P, thr, nseg, g, pos, dpos);
+  };
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  switch (words_per_lane(P, (int)blockDim.x)) {
+    case 4:
+      if (dim == 3) go(I3{}, T_{}, std::integral_constant<int, 4>{});
+      else go(I2{}, T_{}, std::integral_constant<int, 4>{});
+      return;
+    case 3:
+      if (dim == 3) go(I3{}, T_{}, std::integral_constant<int, 3>{});
+      else go(I2{}, T_{}, std::integral_constant<int, 3>{});
+      return;
+    case 2:
+      if (dim == 3) go(I3{}, T_{}, std::integral_constant<int, 2>{});
+      else go(I2{}, T_{}, std::integral_constant<int, 2>{});
+      return;
+    default:
+      if (dim == 3) {
+        if (full) go(I3{}, T_{}, std::integral_constant<int, 1>{});
+        else go(I3{}, F_{}, std::integral_constant<int, 1>{});
+      } else {
+        if (full) go(I2{}, T_{}, std::integral_constant<int, 1>{});
+        else go(I2{}, F_{}, std::integral_constant<int, 1>{});
+      }
+  }
+}
+
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 4)))
+march_kernel(const JobDev* J, int nseg, uint32_t g, int pos, int dpos, int work) {
+  march_body<true>(J, nseg, g, pos, dpos, work);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+march_fixup_kernel(const JobDev* J, int nseg, uint32_t g, int pos, int dpos) {
+  march_body<false>(J, nseg, g, pos, dpos, 0);
+}
+
 // Initial spins of every trajectory, written straight to HBM.
 __global__ void __launch_bounds__(256) stream_init_kernel(const JobDev* J, int lanes) {
   const JP P = load_jp(J);
@@ -1113,6 +1474,22 @@ int ee_k_launch_stream_sweep(const ee::JobDev* job, int n_traj, int lanes, int c
   // one-dimensional grid: bx blocks per trajectory, remapped per XCD in the kernel
   hipLaunchKernelGGL(stream_sweep_kernel, dim3(bx * n_traj), dim3(256), 0, (hipStream_t)stream, job, lanes, c, g,
                      pos, dpos, work);
+  return (int)hipGetLastError();
+}
+
+int ee_k_march_lds_bytes(int plane_words) { return kMarchSlots * plane_words * 4 + 32; }
+
+int ee_k_launch_march(const ee::JobDev* job, int n_traj, int n_replicas, int nseg, int block, int plane_words,
+                      uint32_t g, int pos, int dpos, int work, void* stream) {
+  const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&march_kernel),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, ee_k_max_lds_bytes());
+  if (attr != hipSuccess) return (int)attr;
+  hipLaunchKernelGGL(march_kernel, dim3(n_traj * n_replicas * nseg), dim3(block), ee_k_march_lds_bytes(plane_words),
+                     (hipStream_t)stream, job, nseg, g, pos, dpos, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(march_fixup_kernel, dim3(n_traj * nseg * 2), dim3(256), 32, (hipStream_t)stream, job, nseg, g,
+                     pos, dpos);
   return (int)hipGetLastError();
 }
 

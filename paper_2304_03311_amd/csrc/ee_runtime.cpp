@@ -303,9 +303,62 @@ int stream_lanes(const ee_job* j) {
   return nrg * GW;
 }
 
+// Words of one plane of the plane-marching kernel (one replica, one t,
+// both colours, all y): a slot of its LDS ring.
+int plane_words(const ee_job* j) { return 2 * j->d.ly * j->L.G; }
+
+// Workgroup size of the marching kernel: a lane per row group of up to four
+// words of one colour, and enough lanes that each prefetches at most four
+// transfer units (4 words, or 1 word for rows of other lengths) of a plane.
+int march_block(const ee_job* j) {
+  const long items = (long)j->d.ly * ((j->L.G + 3) / 4);
+  const long units = (j->L.G % 4 == 0) ? plane_words(j) / 4 : plane_words(j);
+  const long lanes = std::max(items, (units + 3) / 4);
+  return (int)std::max(64L, std::min(1024L, (lanes + 63) / 64 * 64));
+}
+
+// Segments per trajectory of the plane-marching kernel for this job, or 0 if
+// the two-pass kernel runs it.  The march reads and writes each plane once
+// per sweep (2 B per site against the two-pass kernel's 3 B), but both
+// kernels are bound by their issue rate and latency rather than by HBM,
+// and the march, with one row per lane between barriers, runs slower
+// (96^3, n = 2, 256 trajectories: 828 attempts/ns against 1213), so it runs
+// only when EE_LAUNCH_MARCH asks for it.  A workgroup marches one segment of
+// one replica of one trajectory, and each segment boundary costs a fix-up
+// pass over two planes; without a segment count in grid_blocks the count
+// minimises rounds x (planes per segment + 3) over the workgroups resident
+// at once (by LDS and by 16 waves per CU).
+int march_segments(const ee_job* j) {
+  if (j->cfg.flags & EE_LAUNCH_TWO_PASS) return 0;
+  const int lds = ee_k_march_lds_bytes(plane_words(j));
+  if (lds > ee_k_max_lds_bytes()) return (j->cfg.flags & EE_LAUNCH_MARCH) ? -1 : 0;
+  if (!(j->cfg.flags & EE_LAUNCH_MARCH)) return 0;
+  const int max_seg = std::max(1, j->d.lt / 2);
+  if (j->cfg.grid_blocks > 0) return std::min(j->cfg.grid_blocks, max_seg);
+  const int waves = (march_block(j) + 63) / 64;
+  const int per_cu = std::max(1, std::min(160 * 1024 / lds, 16 / waves));
+  const long slots = (long)device_info().cus * per_cu;
+  const long pairs = (long)j->d.n_traj * j->d.n_replicas;
+  int best = 1;
+  double best_cost = 1e300;
+  for (int k = 1; k <= std::min(max_seg, 64); ++k) {
+    const double rounds = (double)((pairs * k + slots - 1) / slots);
+    const double cost = rounds * ((double)j->d.lt / k + 3.0);
+    if (cost < best_cost * 0.999) {
+      best_cost = cost;
+      best = k;
+    }
+  }
+  return best;
+}
+
 ee_status stream_sweeps(ee_job* j, int n_sweeps, bool protocol) {
   const int lanes = stream_lanes(j);
   const int nt = j->d.n_traj;
+  const int nseg = march_segments(j);
+  if (nseg < 0)
+    return fail(EE_EUNSUPPORTED, "EE_LAUNCH_MARCH: a plane ring of %d bytes exceeds the %d bytes of LDS",
+                ee_k_march_lds_bytes(plane_words(j)), ee_k_max_lds_bytes());
   int rc = 0;
   if (protocol) rc = ee_k_launch_zero_work(j->dev_jobdev(), nt, j->stream);
   uint32_t g = (uint32_t)j->g;
@@ -314,6 +367,11 @@ ee_status stream_sweeps(ee_job* j, int n_sweeps, bool protocol) {
   const int dpos = protocol ? (rev ? -1 : 1) : 0;
   for (int s = 0; s < n_sweeps && rc == 0; ++s, ++g) {
     const int pos = protocol ? (rev ? N - 1 - s : s + 1) : (rev ? N : 0);
+    if (nseg > 0) {
+      rc = ee_k_launch_march(j->dev_jobdev(), nt, j->d.n_replicas, nseg, march_block(j), plane_words(j), g, pos,
+                             dpos, protocol ? 1 : 0, j->stream);
+      continue;
+    }
     rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 0, g, pos, dpos, protocol ? 1 : 0, j->stream);
     if (rc == 0) rc = ee_k_launch_stream_sweep(j->dev_jobdev(), nt, lanes, 1, g, pos, dpos, 0, j->stream);
   }
@@ -350,8 +408,10 @@ ee_status check_cfg(const ee_launch_cfg* cfg) {
   if (cfg->lds_bytes < 0 || cfg->lds_bytes > ee_k_max_lds_bytes())
     return fail(EE_EINVAL, "lds_bytes must be in [0, %d]", ee_k_max_lds_bytes());
   if (cfg->grid_blocks < 0) return fail(EE_EINVAL, "grid_blocks must be >= 0");
-  if (cfg->flags & ~EE_LAUNCH_STREAMING)
+  if (cfg->flags & ~(EE_LAUNCH_STREAMING | EE_LAUNCH_MARCH | EE_LAUNCH_TWO_PASS))
     return fail(EE_EINVAL, "unknown launch flags 0x%x", cfg->flags);
+  if ((cfg->flags & EE_LAUNCH_MARCH) && (cfg->flags & EE_LAUNCH_TWO_PASS))
+    return fail(EE_EINVAL, "EE_LAUNCH_MARCH and EE_LAUNCH_TWO_PASS exclude each other");
   return EE_OK;
 }
 
@@ -685,11 +745,14 @@ ee_status ee_job_set_launch(ee_job* job, const ee_launch_cfg* cfg) {
   ee_status s = check_cfg(cfg);
   if (s) return s;
   if (job->state == SERVED) return fail(EE_ESTATE, "the job is on a server that has not reported it done");
-  const bool force_stream = cfg && (cfg->flags & EE_LAUNCH_STREAMING);
+  const bool force_stream = cfg && (cfg->flags & (EE_LAUNCH_STREAMING | EE_LAUNCH_MARCH | EE_LAUNCH_TWO_PASS));
   if (force_stream && job->d.spin_format != EE_SPINS_INT8)
     return fail(EE_EUNSUPPORTED, "the streaming path needs EE_SPINS_INT8 storage");
   if (force_stream && job->spins_exist && !job->streaming)
     return fail(EE_ESTATE, "switch to the streaming path before the first ee_thermalize");
+  if (cfg && (cfg->flags & EE_LAUNCH_MARCH) && ee_k_march_lds_bytes(plane_words(job)) > ee_k_max_lds_bytes())
+    return fail(EE_EUNSUPPORTED, "EE_LAUNCH_MARCH: a plane ring of %d bytes exceeds the %d bytes of LDS",
+                ee_k_march_lds_bytes(plane_words(job)), ee_k_max_lds_bytes());
   job->cfg = cfg ? *cfg : ee_launch_cfg{0, 0, 0, 1, 0};
   job->streaming = force_stream || !fits_on_chip(job->L);
   return EE_OK;

@@ -21,6 +21,8 @@ EE_FLAG_REVERSE = 1
 EE_FLAG_SUBSETS = 2
 EE_FLAG_WHOLE = 4
 EE_LAUNCH_STREAMING = 1
+EE_LAUNCH_MARCH = 2
+EE_LAUNCH_TWO_PASS = 4
 
 
 class ee_job_desc(ctypes.Structure):

@@ -347,7 +347,7 @@ def test_whole_region_descriptions_are_checked():
 def test_launch_flags_are_checked():
     s = ee.JobSpec(dim=2, lt=8, lx=32, ly=1, n=2, beta=0.4, l=2, n_step=4, n_traj=2, seed=1)
     job = ee.Job(s)
-    for flags in (2, 4, 8):
+    for flags in (6, 8, 16):
         with pytest.raises(ee.EEError) as e:
             job.set_launch(dict(flags=flags))
         assert e.value.status == ee.EE_EINVAL
@@ -506,6 +506,71 @@ def test_streaming_with_wide_rows_matches_oracle(kw):
     I_or, sp_or = eo.run(oracle_job(s), 3, want_spins=True)
     assert np.array_equal(job.work(), I_or)
     assert np.array_equal(job.spins(), sp_or)
+    job.close()
+
+
+def _march_segments(lt):
+    return sorted({min(k, max(1, lt // 2)) for k in (1, 2, 3, lt // 2)})
+
+
+@pytest.mark.parametrize("name,kw,n_therm", STREAM_CASES, ids=[c[0] for c in STREAM_CASES])
+def test_marching_path_matches_oracle(name, kw, n_therm):
+    """The plane-marching streaming kernel, forced with 1, 2, 3 and lt/2
+    segments per trajectory (every segment boundary takes the fix-up pass),
+    is bit-identical to the oracle."""
+    s = ee.JobSpec(**kw)
+    I_or, sp_or = eo.run(oracle_job(s), n_therm, want_spins=True)
+    for nseg in _march_segments(s.lt):
+        say(f"[gpu] marching {name} segments={nseg}")
+        job = ee.Job(s)
+        job.set_launch({"flags": ee.EE_LAUNCH_MARCH, "grid_blocks": nseg})
+        job.thermalize(n_therm // 2)
+        job.thermalize(n_therm - n_therm // 2)
+        job.run_protocol()
+        assert np.array_equal(job.work(), I_or), nseg
+        assert np.array_equal(job.spins(), sp_or), nseg
+        check_estimate(job.estimate(), I_or, s, f"marching {name}")
+        job.close()
+
+
+@pytest.mark.parametrize("kw", WIDE_STREAM, ids=[f"lx{kw['lx']}_d{kw['dim']}" for kw in WIDE_STREAM])
+def test_marching_with_wide_rows_matches_oracle(kw):
+    s = ee.JobSpec(**kw)
+    I_or, sp_or = eo.run(oracle_job(s), 3, want_spins=True)
+    for nseg in _march_segments(s.lt):
+        say(f"[gpu] marching wide rows {kw} segments={nseg}")
+        job = ee.Job(s)
+        job.set_launch({"flags": ee.EE_LAUNCH_MARCH, "grid_blocks": nseg})
+        job.thermalize(3)
+        job.run_protocol()
+        assert np.array_equal(job.work(), I_or), nseg
+        assert np.array_equal(job.spins(), sp_or), nseg
+        job.close()
+
+
+def test_streaming_kernel_choice_and_errors():
+    """The marching kernel with the runtime's segment count gives the
+    two-pass kernel's bits on a many-trajectory job; forcing the march where
+    its plane ring exceeds LDS is refused."""
+    s = ee.JobSpec(dim=3, lt=12, lx=32, ly=24, n=2, beta=BC3, l=9, n_step=6, n_traj=64, seed=61)
+    out = []
+    for flags in (ee.EE_LAUNCH_MARCH, ee.EE_LAUNCH_TWO_PASS):
+        say(f"[gpu] kernel choice flags={flags}")
+        job = ee.Job(s)
+        job.set_launch({"flags": flags})
+        job.thermalize(2)
+        job.run_protocol()
+        out.append((job.work(), job.spins()))
+        job.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    I_or, sp_or = eo.run(oracle_job(s), 2, 37, 38, want_spins=True)
+    assert out[0][0][37] == I_or[0] and np.array_equal(out[0][1][37], sp_or[0])
+    # a plane (one replica) of 2 * 128 * 64 words: its five-slot ring is 320 KiB
+    big = ee.JobSpec(dim=3, lt=4, lx=512, ly=128, n=2, beta=BC3, l=3, n_step=2, n_traj=1, seed=62)
+    job = ee.Job(big)
+    with pytest.raises(ee.EEError) as e:
+        job.set_launch({"flags": ee.EE_LAUNCH_MARCH})
+    assert e.value.status == ee.EE_EUNSUPPORTED
     job.close()
 
 
