@@ -50,9 +50,12 @@ from . import analysis, ee, workloads
 
 
 def run_increments(L: int, n_traj: int, n_step: int, n_therm: int, lt_factor: int = 8, seed0: int = 1,
-                   beta: float = workloads.BETA_C_2D):
+                   beta: float = workloads.BETA_C_2D, l_range: tuple | None = None):
+    """The increments l of a 2D cylinder (all of them, or l in [l_range[0],
+    l_range[1])), each job seeded seed0 + l."""
+    lo, hi = l_range if l_range is not None else (0, L)
     specs = [ee.JobSpec(dim=2, lt=lt_factor * L, lx=L, ly=1, n=2, beta=beta, l=l, n_step=n_step,
-                        n_traj=n_traj, seed=seed0 + l) for l in range(L)]
+                        n_traj=n_traj, seed=seed0 + l) for l in range(lo, hi)]
     on_chip = 2 * specs[0].lt * ((L // 2 + 3) // 4) * 4 * 2 <= 160 * 1024 - 256
     t0 = time.perf_counter()
     if on_chip:
@@ -69,8 +72,43 @@ def run_increments(L: int, n_traj: int, n_step: int, n_therm: int, lt_factor: in
             j.run_protocol()
             res.append(j.estimate())
             j.close()
+            print(json.dumps({"L": L, "l": s.l, "dS": res[-1].dS, "dS_err": res[-1].dF_err,
+                              "seconds": time.perf_counter() - t0}), flush=True)
     dt = time.perf_counter() - t0
     return specs, res, dt, on_chip
+
+
+def merge_partials(paths) -> list:
+    """Table 1 rows from partial runs (--l-range): every L whose increments
+    0 .. L-1 the files hold, each exactly once, with one (n_traj, n_step,
+    n_therm)."""
+    parts = {}
+    for p in paths:
+        with open(p) as f:
+            for r in json.load(f):
+                if r.get("partial"):
+                    parts.setdefault(r["L"], []).append(r)
+    rows = []
+    for L, rs in sorted(parts.items()):
+        dS = {}
+        for r in rs:
+            for l, d, e in zip(r["l"], r["dS"], r["dS_err"]):
+                if l in dS:
+                    raise ValueError(f"L = {L}: increment {l} appears twice")
+                dS[l] = (d, e)
+        if sorted(dS) != list(range(L)):
+            raise ValueError(f"L = {L}: increments {sorted(set(range(L)) - set(dS))} are missing")
+        params = {(r["n_traj"], r["n_step"], r["n_therm"]) for r in rs}
+        if len(params) != 1:
+            raise ValueError(f"L = {L}: the partial runs differ in (n_traj, n_step, n_therm): {params}")
+        n_traj, n_step, n_therm = params.pop()
+        row = table1_row(L, np.array([dS[l][0] for l in range(L)]), np.array([dS[l][1] for l in range(L)]))
+        sec = sum(r["seconds"] for r in rs)
+        row.update(n_traj=n_traj, n_step=n_step, n_therm=n_therm, seconds=sec,
+                   attempts_per_ns=sum(r["attempts"] for r in rs) / (sec * 1e9), path=rs[0]["path"],
+                   merged_from=len(rs))
+        rows.append(row)
+    return rows
 
 
 def table1_row(L: int, dS: np.ndarray, dS_err: np.ndarray) -> dict:
@@ -208,11 +246,31 @@ def main(argv=None) -> int:
     ap.add_argument("--n-step", type=int, default=1000)
     ap.add_argument("--n-therm", type=int, default=1000)
     ap.add_argument("--out", default=None, help="write the rows as JSON here")
+    ap.add_argument("--l-range", type=int, nargs=2, default=None, metavar=("LO", "HI"),
+                    help="table1: run only the increments l in [LO, HI) and write them as a partial row")
+    ap.add_argument("--merge", nargs="+", default=None, metavar="FILE",
+                    help="table1: combine partial rows (from --l-range runs) into the rows of their L")
     args = ap.parse_args(argv)
+    if args.merge:
+        rows = merge_partials(args.merge)
+        for row in rows:
+            print(json.dumps({k: v for k, v in row.items() if not isinstance(v, list)}), flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(rows, f)
+        return 0
     import torch
     torch.cuda.set_device(0)
     rows = []
     for L in args.L:
+        if args.experiment == "table1" and args.l_range is not None:
+            specs, res, dt, on_chip = run_increments(L, args.n_traj, args.n_step, args.n_therm,
+                                                     l_range=tuple(args.l_range))
+            rows.append({"partial": True, "L": L, "l": [s.l for s in specs], "dS": [r.dS for r in res],
+                         "dS_err": [r.dF_err for r in res], "attempts": sum(r.attempts for r in res),
+                         "seconds": dt, "n_traj": args.n_traj, "n_step": args.n_step, "n_therm": args.n_therm,
+                         "path": "persistent batch" if on_chip else "HBM streaming"})
+            continue
         if args.experiment == "table1":
             specs, res, dt, on_chip = run_increments(L, args.n_traj, args.n_step, args.n_therm)
             row = table1_row(L, np.array([r.dS for r in res]), np.array([r.dF_err for r in res]))
