@@ -37,7 +37,7 @@ BYTES_PER_ATTEMPT = 2.0
 STREAM_BYTES_PER_ATTEMPT = 3.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_2d64_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_03311_amd", "csrc", f)
-                  for f in ("ee_kernels.hip", "ee_internal.hpp", "ee_dd.hpp")]
+                  for f in ("ee_kernels.hip", "ee_internal.hpp", "ee_dd.hpp", "ee_lanes.hpp")]
 
 
 def kernel_hash() -> str:

@@ -201,18 +201,24 @@ EE_HDI LanePM make_lane_pm(const JP& P, int lt_, int T) {
 }
 
 
-// Words per lane for a job and slot size of T lanes: the widest W <= 4
-// that divides the row's words, still gives every row a lane group and
-// leaves no lane of the slot without a row (rows of exactly three words
-// take W = 3 on the same condition).  A slot with more lanes than a wider
-// W has row groups (a small lattice, latency-bound) takes the narrower W:
-// its rows then spread over all lanes, and the wave's instruction chain
-// per half-sweep is shorter.
+// Words per lane for a job and slot size of T lanes.  The widest W <= 4
+// that divides the row's words and still gives every row a lane group
+// (rows of exactly three words take W = 3) needs the fewest passes of the
+// slot's lanes over its row groups; of the W that need as many passes, the
+// narrowest is taken: each pass is then a shorter instruction chain, and a
+// slot with more lanes than wide row groups (a small, latency-bound
+// lattice) spreads its rows over all of its lanes.
 EE_HDI int words_per_lane(const JP& P, int T) {
   const int nrows = P.n * P.R;  // rows of one colour of a trajectory
-  if ((P.H & 15) == 0 && T / (P.G / 4) >= 1 && nrows * (P.G / 4) >= T) return 4;
-  if (P.H == 12 && nrows >= T) return 3;
-  return ((P.H & 7) == 0 && T / (P.G / 2) >= 1 && nrows * (P.G / 2) >= T) ? 2 : 1;
+  const auto passes = [&](int W) { return (nrows * (P.G / W) + T - 1) / T; };
+  int W = 1;
+  if ((P.H & 15) == 0 && T / (P.G / 4) >= 1) W = 4;
+  else if (P.H == 12) W = 3;
+  else if ((P.H & 7) == 0 && T / (P.G / 2) >= 1) W = 2;
+  const int p = passes(W);
+  if (W == 4 && passes(2) == p) W = 2;
+  if (W > 1 && passes(1) == p) W = 1;
+  return W;
 }
 
 // Whether the rows of a unit go in parity-major order: the grouped lane map
