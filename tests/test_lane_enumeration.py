@@ -178,14 +178,16 @@ int main() {
         }
         ++cases;
       }
-    // the streaming kernel's map: about four rows per lane, storage order
+    // the streaming kernel's map: r rows per lane, storage order
     const int nrows = s.n * P.R;
     const int Ws = ((P.H & 15) == 0) ? 4 : (P.H == 12) ? 3 : ((P.H & 7) == 0) ? 2 : 1;
-    const int lanes = ((nrows + 3) / 4 > 0 ? (nrows + 3) / 4 : 1) * (P.G / Ws);
-    snprintf(tag, sizeof tag, "stream D%d %dx%dx%d n%d lanes%d W%d", s.dim, s.lt, s.lx, s.ly, s.n, lanes, Ws);
-    CHECK(words_per_lane(P, lanes) == Ws, "%s: the runtime's W differs from the kernel's", tag);
-    walk_lanemap(P, lanes, Ws, false, tag);
-    ++cases;
+    for (int r : {1, 2, 4, 7, 16}) {
+      const int lanes = ((nrows + r - 1) / r) * (P.G / Ws);
+      snprintf(tag, sizeof tag, "stream D%d %dx%dx%d n%d lanes%d W%d", s.dim, s.lt, s.lx, s.ly, s.n, lanes, Ws);
+      CHECK(words_per_lane(P, lanes) == Ws, "%s: the runtime's W differs from the kernel's", tag);
+      walk_lanemap(P, lanes, Ws, false, tag);
+      ++cases;
+    }
   }
   printf("cases %d fails %d\n", cases, fails);
   return fails ? 1 : 0;
