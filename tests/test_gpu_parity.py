@@ -448,6 +448,37 @@ def test_full_size_3d_32cube_sampled():
     bjob.close()
 
 
+def test_full_size_streaming_96cube_sampled():
+    """The two streaming workloads the benchmark times, in its launch
+    configurations: 3D 96^3 (n = 2, N = 100 after 10 thermalisation sweeps)
+    with 32 trajectories on the two-pass kernel and with 256 on the
+    plane-marching kernel (the runtime's segment count).  The random numbers
+    of trajectory j depend on (seed, site, sweep, j) only, so trajectories
+    0..31 of both runs are bit-identical; sampled trajectories of each run
+    are checked against the oracle."""
+    base = dict(dim=3, lt=96, lx=96, ly=96, n=2, beta=workloads.BETA_3D, l=40, n_step=100, seed=5)
+    runs = []
+    for n_traj, flags in ((32, ee.EE_LAUNCH_TWO_PASS), (256, ee.EE_LAUNCH_MARCH)):
+        s = ee.JobSpec(n_traj=n_traj, **base)
+        say(f"[gpu] full 96^3 streaming: {n_traj} trajectories, flags {flags}")
+        job = ee.Job(s)
+        job.set_launch({"flags": flags})
+        job.thermalize(10)
+        job.run_protocol()
+        runs.append((s, job))
+    (s2, two), (sm, mar) = runs
+    assert np.array_equal(two.work(), mar.work()[:32])
+    assert np.array_equal(two.spins(), mar.spins(32))
+    for s, job, j in ((s2, two, 29), (sm, mar, 200)):
+        say(f"[gpu]   sample n_t={s.n_traj} j={j}")
+        I_or, sp_or = eo.run(oracle_job(s), 10, j, j + 1, want_spins=True)
+        assert job.work()[j] == I_or[0]
+        assert np.array_equal(job.spins(j + 1)[j], sp_or[0])
+    for s, job in runs:
+        check_estimate(job.estimate(), job.work(), s, f"96^3 n_t={s.n_traj}")
+        job.close()
+
+
 def test_full_size_24_uneven_jobs_sampled():
     """The 24 uneven jobs (2D L = 24..96, 3D L = 16..32, N = 500..2000) in one
     persistent launch of the benchmark's shape: one sampled trajectory of
