@@ -203,7 +203,8 @@ typedef struct {
                               raised to ceil(lx/8) rounded up to 64 when smaller (one lane
                               per word of a row)                                           */
   int32_t lds_bytes;       /* LDS budget per workgroup (bytes); 0 = default               */
-  int32_t grid_blocks;     /* persistent workgroups; 0 = one wave of the whole GPU          */
+  int32_t grid_blocks;     /* persistent workgroups; 0 = one wave of the whole GPU (with
+                              EE_LAUNCH_MARCH: segments per trajectory, 0 = the runtime's) */
   int32_t use_graph;       /* 1 = record/replay a HIP graph (default), 0 = direct launches  */
   uint32_t flags;          /* EE_LAUNCH_* bits                                            */
 } ee_launch_cfg;
