@@ -214,7 +214,12 @@ __device__ __forceinline__ uint32_t half16(uint32_t word, int hi) { return hi ? 
 // to the cut (t = 0, 1) is compiled in; without it the row must have t > 1.
 // XG: the glued partner row is at Lo + og_in (a layout other than the
 // colour-plane storage order), with the parity known only at run time.
-template <int DIM, bool FULL, int W, int PAR, bool CUT, bool XG = false>
+// LA (lookahead): the row's Philox outputs (phase 1) come in preU, computed
+// during the previous half-sweep, and this update computes those of the
+// same row in sweep g_next with counter word c3_next into nextU.  They do
+// not depend on spins, so that chain overlaps this row's loads and
+// decisions instead of lengthening the next half-sweep.
+template <int DIM, bool FULL, int W, int PAR, bool CUT, bool XG = false, bool LA = false>
 __device__ __forceinline__ void row_update(const JP& P, const int w, const int wl, const int wr,
                                            uint32_t* __restrict__ Lc, const uint32_t* __restrict__ Lo,
                                            const uint32_t* __restrict__ thr, const int c, const uint32_t g,
@@ -223,7 +228,9 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
                                            uint32_t* __restrict__ pC, const uint32_t* __restrict__ pO,
                                            const int tmo, const int tpo, const int ymo, const int ypo,
                                            const uint32_t c0, const uint32_t c3, const int og_in = 0,
-                                           const uint32_t* gm_in = nullptr) {
+                                           const uint32_t* gm_in = nullptr, const uint32_t* preU = nullptr,
+                                           uint32_t* nextU = nullptr, const uint32_t g_next = 0,
+                                           const uint32_t c3_next = 0) {
   static_assert(W == 1 || ((W == 2 || W == 3 || W == 4) && FULL), "several words per lane need whole rows");
   constexpr int NC = (W + 1) / 2;  // Philox calls per row: 8 sites each
   const int G = P.G;
@@ -234,6 +241,10 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   const int p = (PAR >= 0) ? PAR : ((c + t + y) & 1);  // x parity of this row's sites
   uint32_t A[W], B[W], S[W], a[W];
   ld_words<W>(pO, A);
+  if (LA) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) philox10_x02(c0 + k, g_next, j, c3_next, P.key0, P.key1, 0x80008000u, nextU + 4 * k);
+  }
   if (FULL) {
     // the sites' x-1 (p = 0) or x+1 (p = 1) neighbours straddle two words
     const uint32_t E = pO[(p ? wr : wl) - w];
@@ -308,7 +319,12 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   for (int k = 0; k < NC; ++k) {
     // u[0], u[2] arrive as v ^ 0x8000 per field; u[1], u[3] are xored here
     uint32_t u[4];
-    philox10_x02(c0 + k, g, j, c3, P.key0, P.key1, 0x80008000u, u);
+    if (LA) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) u[e] = preU[4 * k + e];
+    } else {
+      philox10_x02(c0 + k, g, j, c3, P.key0, P.key1, 0x80008000u, u);
+    }
     u[1] ^= 0x80008000u;
     u[3] ^= 0x80008000u;
     dmk[k] = 0xFFFFFFFFu;
@@ -545,6 +561,46 @@ __device__ __forceinline__ void rows_pm(const JP& P, const LanePM& lp, uint32_t*
   }
 }
 
+// half_sweep for lanes that own at most one row (small, latency-bound
+// lattices): the row's Philox outputs U were computed during the previous
+// half-sweep, and this one computes those of the next (sweep g_next,
+// colour c_next) into U.
+template <int DIM, bool FULL, bool UJ, int W>
+__device__ __forceinline__ void half_sweep_la(const JP& P, const Lane& ln, uint32_t* __restrict__ L,
+                                              const uint32_t* __restrict__ thr, const int c, const uint32_t g,
+                                              uint32_t j, const int pos, const int dpos, const bool work, int& dI,
+                                              uint32_t* U, const uint32_t g_next, const int c_next) {
+  if (UJ) j = __builtin_amdgcn_readfirstlane(j);
+  if (ln.kstart >= ln.kend) return;
+  const int G = P.G;
+  const int cw = P.n * P.R * G;  // words per colour plane
+  uint32_t* __restrict__ Lc = L + c * cw;
+  const uint32_t* __restrict__ Lo = L + (c ^ 1) * cw;
+  const int LyG = P.ly * G;
+  const int ltLyG = P.lt * LyG;
+  const int ywrap = (P.ly - 1) * G;
+  const int w = ln.w, r = ln.r0, t = ln.t0, y = ln.y0;
+  const int rowbase = ln.rowbase0;
+  const int tpo = LyG - ((t == P.lt - 1) ? ltLyG : 0);
+  const int ymo = (y == 0) ? ywrap : -G;
+  const int ypo = (y == P.ly - 1) ? -ywrap : G;
+  const uint32_t c0 = (uint32_t)((t * P.ly + y) * P.G8 + (w >> 1));
+  const uint32_t c3 = (1u << 28) | ((uint32_t)r << 1) | (uint32_t)c;
+  const uint32_t c3n = (1u << 28) | ((uint32_t)r << 1) | (uint32_t)c_next;
+  constexpr int NC = (W + 1) / 2;
+  uint32_t Un[4 * NC];
+  const auto row = [&](auto cut) {
+    const int tmo = -LyG + ((decltype(cut)::value && t == 0) ? ltLyG : 0);
+    row_update<DIM, FULL, W, -1, decltype(cut)::value, false, true>(
+        P, w, ln.wl, ln.wr, Lc, Lo, thr, c, g, j, pos, dpos, work, dI, r, t, y, Lc + rowbase + w, Lo + rowbase + w,
+        tmo, tpo, ymo, ypo, c0, c3, 0, nullptr, U, Un, g_next, c3n);
+  };
+  if (__builtin_amdgcn_ballot_w64(t <= 1) != 0) row(std::true_type{});
+  else row(std::false_type{});
+#pragma unroll
+  for (int e = 0; e < 4 * NC; ++e) U[e] = Un[e];
+}
+
 template <int DIM, bool UJ, int W>
 __device__ __forceinline__ void half_sweep_pm(const JP& P, const LanePM& lp, uint32_t* __restrict__ L,
                                               const uint32_t* __restrict__ thr, const int c,
@@ -660,15 +716,48 @@ __device__ __forceinline__ void run_unit(const JP& P, uint32_t* lds, int* s_dI, 
   const bool proto = (flags & ee::kFlagProto) != 0;
   const int n_sweeps = n_therm + (proto ? P.N : 0);
   const int dpos_p = P.reverse ? -1 : 1;
-  for (int s = 0; s < n_sweeps; ++s, ++g) {
-    const int k = s - n_therm;
-    const bool in_proto = k >= 0;
-    const int pos = in_proto ? (P.reverse ? P.N - 1 - k : k + 1) : pos0;
-    const int dpos = in_proto ? dpos_p : 0;
+  // Lane-map order with at most one row per lane (uniform, from the shape:
+  // the row slots of a replica cover its rows): the Philox outputs of each
+  // half-sweep are computed during the one before.
+  bool lookahead = false;
+  if constexpr (!PM) {
+    const int slots = T / (P.G / W);
+    lookahead = n_sweeps > 0 && ((slots >= P.n) ? (slots / P.n >= P.R) : (slots >= P.n * P.R));
+  }
+  if (lookahead) {
+    constexpr int NC = (W + 1) / 2;
+    uint32_t U[4 * NC];
+    if (on) {
+      const uint32_t jj = UJ ? __builtin_amdgcn_readfirstlane(j) : j;
+      const uint32_t c0 = (uint32_t)((ln.t0 * P.ly + ln.y0) * P.G8 + (ln.w >> 1));
+      const uint32_t c3 = (1u << 28) | ((uint32_t)ln.r0 << 1);  // colour 0
+#pragma unroll
+      for (int k = 0; k < NC; ++k) philox10_x02(c0 + k, g, jj, c3, P.key0, P.key1, 0x80008000u, U + 4 * k);
+    }
+    for (int s = 0; s < n_sweeps; ++s, ++g) {
+      const int k = s - n_therm;
+      const bool in_proto = k >= 0;
+      const int pos = in_proto ? (P.reverse ? P.N - 1 - k : k + 1) : pos0;
+      const int dpos = in_proto ? dpos_p : 0;
 #pragma unroll 1
-    for (int c = 0; c < 2; ++c) {
-      if (on) half(c, g, pos, dpos, in_proto && c == 0);
-      __syncthreads();
+      for (int c = 0; c < 2; ++c) {
+        if (on)
+          half_sweep_la<DIM, FULL, UJ, W>(P, ln, L, s_thr, c, g, j, pos, dpos, in_proto && c == 0, dI, U,
+                                          c == 0 ? g : g + 1, c ^ 1);
+        __syncthreads();
+      }
+    }
+  } else {
+    for (int s = 0; s < n_sweeps; ++s, ++g) {
+      const int k = s - n_therm;
+      const bool in_proto = k >= 0;
+      const int pos = in_proto ? (P.reverse ? P.N - 1 - k : k + 1) : pos0;
+      const int dpos = in_proto ? dpos_p : 0;
+#pragma unroll 1
+      for (int c = 0; c < 2; ++c) {
+        if (on) half(c, g, pos, dpos, in_proto && c == 0);
+        __syncthreads();
+      }
     }
   }
   if (proto) {
