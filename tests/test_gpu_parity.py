@@ -344,6 +344,35 @@ def test_whole_region_descriptions_are_checked():
     assert ee.ee_job_footprint(ee.JobSpec(l=8, **base).desc()) > 0
 
 
+ONE_ROW_SPECS = [
+    dict(dim=2, lt=8, lx=6, ly=1, n=2, beta=0.5, l=2, n_step=20, n_traj=6, seed=3),
+    dict(dim=2, lt=2, lx=2, ly=1, n=2, beta=0.7, l=1, n_step=9, n_traj=7, seed=9),
+    dict(dim=2, lt=12, lx=16, ly=1, n=2, beta=BC2, l=5, n_step=30, n_traj=9, seed=4, reverse=True),
+    dict(dim=2, lt=16, lx=16, ly=1, n=2, beta=BC2, l=4, n_step=40, n_traj=8, seed=1),
+    dict(dim=3, lt=4, lx=6, ly=2, n=2, beta=0.3, l=5, n_step=9, n_traj=5, seed=13),
+    dict(dim=3, lt=4, lx=8, ly=4, n=3, beta=BC3, l=0, n_step=6, n_traj=3, seed=15),
+    dict(dim=2, lt=6, lx=8, ly=1, n=3, beta=0.5, l=8, n_step=6, n_traj=4, seed=52, whole=True, reverse=True),
+    dict(dim=3, lt=4, lx=16, ly=6, n=2, beta=0.23, l=9, n_step=18, n_traj=4, seed=17, subsets=True, reverse=True),
+]
+
+
+@pytest.mark.parametrize("kw", ONE_ROW_SPECS, ids=[f"D{k['dim']}_{k['lt']}x{k['lx']}x{k['ly']}_n{k['n']}"
+                                                    for k in ONE_ROW_SPECS])
+def test_one_row_per_lane_lookahead_matches_oracle(kw):
+    """Launch shapes in which every lane owns at most one row (the lane-map
+    order with the Philox outputs computed a half-sweep ahead), from one to
+    sixteen waves per workgroup: bit-identical to the oracle."""
+    s = ee.JobSpec(**kw)
+    I_or, sp_or = eo.run(oracle_job(s), 5, want_spins=True)
+    for block in (64, 256, 1024):
+        say(f"[gpu] one row per lane {kw} block={block}")
+        job = ee.Job(s)
+        ee.batch_run([job], 5, cfg=dict(block_threads=block))
+        assert np.array_equal(job.work(), I_or), block
+        assert np.array_equal(job.spins(), sp_or), block
+        job.close()
+
+
 def test_launch_flags_are_checked():
     s = ee.JobSpec(dim=2, lt=8, lx=32, ly=1, n=2, beta=0.4, l=2, n_step=4, n_traj=2, seed=1)
     job = ee.Job(s)
