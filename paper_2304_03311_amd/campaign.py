@@ -214,6 +214,36 @@ def direct_vs_reverse(dim: int, L: int, lt_factor: int, n_traj: int, n_step: int
             "err_forward": [a.dF_err for a in f], "err_reverse": [b.dF_err for b in r]}
 
 
+def direct_vs_reverse_n(L: int, lt_factor: int, l: int, n_traj: int, n_steps, n_therm: int,
+                        beta: float | None = None, seed0: int = 1) -> dict:
+    """2D, one increment l -> l+1 at a fixed n_t, forward and reverse, for a
+    range of protocol lengths N (Sec. 4, the direct/reverse comparison at
+    fixed n_t over N, and the work distributions, which narrow towards the
+    quasi-static limit as N grows).  Per N: Delta F forward, Delta F reverse
+    (its negative estimates the same quantity), their pull, and the mean and
+    variance of the work of both."""
+    beta = workloads.BETA_C_2D if beta is None else beta
+    lt = lt_factor * L
+    specs = []
+    for i, N in enumerate(n_steps):
+        for rev in (False, True):
+            specs.append(ee.JobSpec(dim=2, lt=lt, lx=L, ly=1, n=2, beta=beta, l=l, n_step=N, n_traj=n_traj,
+                                    seed=seed0 + 2 * i + int(rev), reverse=rev))
+    t0 = time.perf_counter()
+    res = run_specs(specs, n_therm)
+    dt = time.perf_counter() - t0
+    rows = []
+    for i, N in enumerate(n_steps):
+        f, r = res[2 * i], res[2 * i + 1]
+        err = math.hypot(f.dF_err, r.dF_err)
+        rows.append({"N": N, "dF_forward": f.dF, "err_forward": f.dF_err, "dF_reverse": r.dF,
+                     "err_reverse": r.dF_err, "pull": (f.dF + r.dF) / err if err > 0 else 0.0,
+                     "w_mean_forward": f.w_mean, "w_var_forward": f.w_var, "w_mean_reverse": r.w_mean,
+                     "w_var_reverse": r.w_var})
+    return {"experiment": "direct vs reverse over N", "dim": 2, "L": L, "L_tau": lt, "l": l, "beta": beta,
+            "n_traj": n_traj, "n_therm": n_therm, "seconds": dt, "rows": rows}
+
+
 def protocol1_vs_2(L: int, lt_factor: int, n_traj: int, n_step: int, n_therm: int, beta: float | None = None,
                    seed0: int = 1) -> dict:
     """3D: every increment with the L links of the ramped row moved at once
@@ -237,13 +267,16 @@ def protocol1_vs_2(L: int, lt_factor: int, n_traj: int, n_step: int, n_therm: in
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--experiment", default="table1", choices=["table1", "zero3d", "dirrev", "proto12"])
+    ap.add_argument("--experiment", default="table1", choices=["table1", "zero3d", "dirrev", "dirrev_n", "proto12"])
     ap.add_argument("--dim", type=int, default=2, help="dirrev: lattice dimension")
     ap.add_argument("--L", type=int, nargs="+", default=[32, 64])
     ap.add_argument("--lt-factor", type=int, nargs="+", default=None,
                     help="L_tau / L (table1: 8; zero3d: 1 4; dirrev: 8 in 2D, 4 in 3D; proto12: 4)")
     ap.add_argument("--n-traj", type=int, default=1024)
     ap.add_argument("--n-step", type=int, default=1000)
+    ap.add_argument("--n-steps", type=int, nargs="+", default=[10, 20, 50, 100, 200, 500, 1000, 2000, 5000],
+                    help="dirrev_n: the protocol lengths N")
+    ap.add_argument("--l", type=int, default=None, help="dirrev_n: the increment l -> l+1 (default L/8 - 1)")
     ap.add_argument("--n-therm", type=int, default=1000)
     ap.add_argument("--out", default=None, help="write the rows as JSON here")
     ap.add_argument("--l-range", type=int, nargs=2, default=None, metavar=("LO", "HI"),
@@ -282,6 +315,10 @@ def main(argv=None) -> int:
         if args.experiment == "zero3d":
             for f in (args.lt_factor or [1, 4]):
                 rows.append(zero_temperature(3, L, f, args.n_traj, args.n_step, args.n_therm))
+        elif args.experiment == "dirrev_n":
+            f = (args.lt_factor or [8])[0]
+            rows.append(direct_vs_reverse_n(L, f, max(0, L // 8 - 1) if args.l is None else args.l, args.n_traj,
+                                            args.n_steps, args.n_therm))
         elif args.experiment == "dirrev":
             f = (args.lt_factor or [8 if args.dim == 2 else 4])[0]
             rows.append(direct_vs_reverse(args.dim, L, f, args.n_traj, args.n_step, args.n_therm))
@@ -289,7 +326,7 @@ def main(argv=None) -> int:
             f = (args.lt_factor or [4])[0]
             rows.append(protocol1_vs_2(L, f, args.n_traj, args.n_step, args.n_therm))
     for row in rows:
-        brief = {k: v for k, v in row.items() if not isinstance(v, list)}
+        brief = {k: v for k, v in row.items() if not isinstance(v, list) or k == "rows"}
         print(json.dumps(brief), flush=True)
     if args.out:
         with open(args.out, "w") as f:

@@ -173,3 +173,24 @@ def test_protocol1_and_protocol2_agree_over_all_x():
     print(f"[gpu] protocol 1 vs 2, 3D L=16: chi2/nu = {r['chi2_per_dof']:.2f} over {r['dof']}",
           file=sys.stderr, flush=True)
     assert r["chi2_per_dof"] < 2.5
+
+
+def test_direct_and_reverse_agree_over_protocol_lengths():
+    """Sec. 4 compares the direct and reverse realisations of one increment
+    at a fixed n_t over a range of protocol lengths N: they agree within the
+    statistical errors at every N, and the work distributions narrow as N
+    grows (towards the quasi-static limit), with <W> >= Delta F for each
+    (Jensen's inequality applied to Jarzynski's equality, App. A)."""
+    from paper_2304_03311_amd import campaign
+    r = campaign.direct_vs_reverse_n(16, 8, 2, 512, [25, 100, 400], 5000)
+    for row in r["rows"]:
+        print(f"[gpu] N={row['N']}: dF fwd {row['dF_forward']:.5f}({row['err_forward']:.5f}) "
+              f"-rev {-row['dF_reverse']:.5f}({row['err_reverse']:.5f}) pull {row['pull']:+.2f}; "
+              f"var W fwd {row['w_var_forward']:.4g} rev {row['w_var_reverse']:.4g}", file=sys.stderr, flush=True)
+    for row in r["rows"]:
+        assert abs(row["pull"]) < 4.0
+        assert row["w_mean_forward"] >= row["dF_forward"] - 1e-12
+        assert row["w_mean_reverse"] >= row["dF_reverse"] - 1e-12
+    for key in ("w_var_forward", "w_var_reverse"):
+        v = [row[key] for row in r["rows"]]
+        assert v[0] > v[1] > v[2] > 0
