@@ -134,25 +134,31 @@ def table1_row(L: int, dS: np.ndarray, dS_err: np.ndarray) -> dict:
             "x": x.tolist(), "C": C.tolist(), "C_err": err.tolist()}
 
 
-def run_specs(specs, n_therm: int):
+def run_specs(specs, n_therm: int, want_work: bool = False):
     """Results of the jobs: one persistent batch for those on chip, the
-    per-job path for the others."""
+    per-job path for the others (with want_work, also each job's integer
+    works I_j)."""
     on = [s for s in specs if ee.ee_job_on_chip(s.desc())]
     off = [s for s in specs if not ee.ee_job_on_chip(s.desc())]
-    res = {}
+    res, work = {}, {}
     if on:
         jobs = [ee.Job(s) for s in on]
         ee.batch_run(jobs, n_therm)
         for s, j in zip(on, jobs):
             res[id(s)] = j.estimate()
+            if want_work:
+                work[id(s)] = j.work()
             j.close()
     for s in off:
         j = ee.Job(s)
         j.thermalize(n_therm)
         j.run_protocol()
         res[id(s)] = j.estimate()
+        if want_work:
+            work[id(s)] = j.work()
         j.close()
-    return [res[id(s)] for s in specs]
+    out = [res[id(s)] for s in specs]
+    return (out, [work[id(s)] for s in specs]) if want_work else out
 
 
 def _increments(dim: int, L: int, lt: int, beta: float, n_traj: int, n_step: int, seed0: int, **kw):
@@ -230,16 +236,23 @@ def direct_vs_reverse_n(L: int, lt_factor: int, l: int, n_traj: int, n_steps, n_
             specs.append(ee.JobSpec(dim=2, lt=lt, lx=L, ly=1, n=2, beta=beta, l=l, n_step=N, n_traj=n_traj,
                                     seed=seed0 + 2 * i + int(rev), reverse=rev))
     t0 = time.perf_counter()
-    res = run_specs(specs, n_therm)
+    res, works = run_specs(specs, n_therm, want_work=True)
     dt = time.perf_counter() - t0
     rows = []
     for i, N in enumerate(n_steps):
         f, r = res[2 * i], res[2 * i + 1]
         err = math.hypot(f.dF_err, r.dF_err)
+        # work distributions W = -(beta/N) I_j (App. A): the forward one and
+        # the reverse one mirrored (W -> -W), on one set of 40 bins
+        wf = -(beta / N) * works[2 * i].astype(np.float64)
+        wr = (beta / N) * works[2 * i + 1].astype(np.float64)
+        edges = np.linspace(min(wf.min(), wr.min()), max(wf.max(), wr.max()), 41)
         rows.append({"N": N, "dF_forward": f.dF, "err_forward": f.dF_err, "dF_reverse": r.dF,
                      "err_reverse": r.dF_err, "pull": (f.dF + r.dF) / err if err > 0 else 0.0,
                      "w_mean_forward": f.w_mean, "w_var_forward": f.w_var, "w_mean_reverse": r.w_mean,
-                     "w_var_reverse": r.w_var})
+                     "w_var_reverse": r.w_var, "hist_edges": edges.tolist(),
+                     "hist_forward": np.histogram(wf, edges)[0].tolist(),
+                     "hist_reverse_mirrored": np.histogram(wr, edges)[0].tolist()})
     return {"experiment": "direct vs reverse over N", "dim": 2, "L": L, "L_tau": lt, "l": l, "beta": beta,
             "n_traj": n_traj, "n_therm": n_therm, "seconds": dt, "rows": rows}
 
