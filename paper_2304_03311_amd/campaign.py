@@ -280,11 +280,13 @@ def protocol1_vs_2(L: int, lt_factor: int, n_traj: int, n_step: int, n_therm: in
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--experiment", default="table1", choices=["table1", "zero3d", "dirrev", "dirrev_n", "proto12"])
-    ap.add_argument("--dim", type=int, default=2, help="dirrev: lattice dimension")
+    ap.add_argument("--experiment", default="table1",
+                    choices=["table1", "zero", "zero3d", "dirrev", "dirrev_n", "proto12"])
+    ap.add_argument("--dim", type=int, default=2, help="dirrev, zero: lattice dimension")
     ap.add_argument("--L", type=int, nargs="+", default=[32, 64])
     ap.add_argument("--lt-factor", type=int, nargs="+", default=None,
-                    help="L_tau / L (table1: 8; zero3d: 1 4; dirrev: 8 in 2D, 4 in 3D; proto12: 4)")
+                    help="L_tau / L (table1: 8; zero: 1 2 4 8 in 2D, 1 4 in 3D; zero3d: 1 4; dirrev: 8 in 2D, "
+                         "4 in 3D; proto12: 4)")
     ap.add_argument("--n-traj", type=int, default=1024)
     ap.add_argument("--n-step", type=int, default=1000)
     ap.add_argument("--n-steps", type=int, nargs="+", default=[10, 20, 50, 100, 200, 500, 1000, 2000, 5000],
@@ -325,9 +327,10 @@ def main(argv=None) -> int:
                        attempts_per_ns=att / (dt * 1e9), path="persistent batch" if on_chip else "HBM streaming")
             rows.append(row)
             continue
-        if args.experiment == "zero3d":
-            for f in (args.lt_factor or [1, 4]):
-                rows.append(zero_temperature(3, L, f, args.n_traj, args.n_step, args.n_therm))
+        if args.experiment in ("zero", "zero3d"):
+            dim = 3 if args.experiment == "zero3d" else args.dim
+            for f in (args.lt_factor or ([1, 2, 4, 8] if dim == 2 else [1, 4])):
+                rows.append(zero_temperature(dim, L, f, args.n_traj, args.n_step, args.n_therm))
         elif args.experiment == "dirrev_n":
             f = (args.lt_factor or [8])[0]
             rows.append(direct_vs_reverse_n(L, f, max(0, L // 8 - 1) if args.l is None else args.l, args.n_traj,

@@ -194,3 +194,17 @@ def test_direct_and_reverse_agree_over_protocol_lengths():
     for key in ("w_var_forward", "w_var_reverse"):
         v = [row[key] for row in r["rows"]]
         assert v[0] > v[1] > v[2] > 0
+
+
+def test_2d_zero_temperature_condition():
+    """Sec. 4 zero-temperature check: with L_tau = L the replicas see a
+    finite-temperature state, S_2(L) stays positive and C(x) + C(1-x) is far
+    from zero; with L_tau = 8L both vanish within errors."""
+    from paper_2304_03311_amd import campaign
+    hot = campaign.zero_temperature(2, 16, 1, 1024, 1000, 5000)
+    cold = campaign.zero_temperature(2, 16, 8, 1024, 1000, 5000)
+    for r in (hot, cold):
+        print(f"[gpu] 2D L=16 L_tau={r['L_tau']}: S_2(L) = {r['S_L']:.4f}({r['S_L_err']:.4f}), "
+              f"C(x)+C(1-x) chi2/pair = {r['chi2_symmetry']:.2f}", file=sys.stderr, flush=True)
+    assert hot["S_L"] > 10 * hot["S_L_err"] and hot["chi2_symmetry"] > 10
+    assert abs(cold["S_L"]) < 3 * cold["S_L_err"] and cold["chi2_symmetry"] < 2.5
