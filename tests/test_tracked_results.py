@@ -17,7 +17,8 @@ TABLE1 = {r["L"]: r for r in json.load(open(os.path.join(ROOT, "tests", "golden"
     "table1_fit_k"]["rows"]}
 
 
-@pytest.mark.parametrize("name", ["table1_2d_L32", "table1_2d_L64", "table1_2d_L64_nt4096", "table1_2d_L128"])
+@pytest.mark.parametrize("name", ["table1_2d_L32", "table1_2d_L32_th40k", "table1_2d_L64", "table1_2d_L64_nt4096",
+                                  "table1_2d_L128"])
 def test_table1_rows_refit_and_agree_with_the_paper(name):
     rows = json.load(open(os.path.join(ROOT, "results", f"{name}.json")))
     assert len(rows) == 1
