@@ -257,6 +257,24 @@ def direct_vs_reverse_n(L: int, lt_factor: int, l: int, n_traj: int, n_steps, n_
             "n_traj": n_traj, "n_therm": n_therm, "seconds": dt, "rows": rows}
 
 
+def thermalisation_scan(L: int, lt_factor: int, l: int, n_traj: int, n_step: int, therms,
+                        beta: float | None = None, seed0: int = 1) -> dict:
+    """2D, one increment l -> l+1 after each number of thermalisation sweeps
+    in therms (the same seed: every run continues the same chains, so the
+    estimates drift only as the starting ensemble relaxes)."""
+    beta = workloads.BETA_C_2D if beta is None else beta
+    rows = []
+    t0 = time.perf_counter()
+    for nt in therms:
+        spec = ee.JobSpec(dim=2, lt=lt_factor * L, lx=L, ly=1, n=2, beta=beta, l=l, n_step=n_step,
+                          n_traj=n_traj, seed=seed0 + l)
+        r = run_specs([spec], nt)[0]
+        rows.append({"n_therm": nt, "dS": r.dS, "dS_err": r.dF_err, "w_mean": r.w_mean, "w_var": r.w_var})
+        print(json.dumps({"L": L, "l": l, **rows[-1]}), flush=True)
+    return {"experiment": "thermalisation scan", "dim": 2, "L": L, "L_tau": lt_factor * L, "l": l, "beta": beta,
+            "n_traj": n_traj, "n_step": n_step, "seconds": time.perf_counter() - t0, "rows": rows}
+
+
 def protocol1_vs_2(L: int, lt_factor: int, n_traj: int, n_step: int, n_therm: int, beta: float | None = None,
                    seed0: int = 1) -> dict:
     """3D: every increment with the L links of the ramped row moved at once
@@ -281,7 +299,7 @@ def protocol1_vs_2(L: int, lt_factor: int, n_traj: int, n_step: int, n_therm: in
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--experiment", default="table1",
-                    choices=["table1", "zero", "zero3d", "dirrev", "dirrev_n", "proto12"])
+                    choices=["table1", "zero", "zero3d", "dirrev", "dirrev_n", "therm", "proto12"])
     ap.add_argument("--dim", type=int, default=2, help="dirrev, zero: lattice dimension")
     ap.add_argument("--L", type=int, nargs="+", default=[32, 64])
     ap.add_argument("--lt-factor", type=int, nargs="+", default=None,
@@ -291,7 +309,9 @@ def main(argv=None) -> int:
     ap.add_argument("--n-step", type=int, default=1000)
     ap.add_argument("--n-steps", type=int, nargs="+", default=[10, 20, 50, 100, 200, 500, 1000, 2000, 5000],
                     help="dirrev_n: the protocol lengths N")
-    ap.add_argument("--l", type=int, default=None, help="dirrev_n: the increment l -> l+1 (default L/8 - 1)")
+    ap.add_argument("--l", type=int, default=None, help="dirrev_n, therm: the increment l -> l+1 (default L/8 - 1)")
+    ap.add_argument("--therms", type=int, nargs="+", default=[2500, 5000, 10000, 20000, 40000, 80000],
+                    help="therm: the thermalisation lengths")
     ap.add_argument("--n-therm", type=int, default=1000)
     ap.add_argument("--out", default=None, help="write the rows as JSON here")
     ap.add_argument("--l-range", type=int, nargs=2, default=None, metavar=("LO", "HI"),
@@ -331,6 +351,10 @@ def main(argv=None) -> int:
             dim = 3 if args.experiment == "zero3d" else args.dim
             for f in (args.lt_factor or ([1, 2, 4, 8] if dim == 2 else [1, 4])):
                 rows.append(zero_temperature(dim, L, f, args.n_traj, args.n_step, args.n_therm))
+        elif args.experiment == "therm":
+            f = (args.lt_factor or [8])[0]
+            rows.append(thermalisation_scan(L, f, max(0, L // 8 - 1) if args.l is None else args.l, args.n_traj,
+                                            args.n_step, args.therms))
         elif args.experiment == "dirrev_n":
             f = (args.lt_factor or [8])[0]
             rows.append(direct_vs_reverse_n(L, f, max(0, L // 8 - 1) if args.l is None else args.l, args.n_traj,
