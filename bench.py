@@ -113,7 +113,9 @@ def serving_run(n_jobs: int, rate: float = 200.0) -> dict:
     stream = workloads.serving_stream(n_jobs, rate, seed=1, **workloads.SERVE_MIX)
     offered = sum(s.n_traj * s.sites * (workloads.N_THERM + s.n_step) for _, s in stream) / stream[-1][0]
     out = {"rate_jobs_per_s": rate, "offered_attempts_per_ns": offered / 1e9, "mix": workloads.SERVE_MIX,
-           "launch": workloads.SERVE_LAUNCH, "hbm_budget_bytes": workloads.SERVE_HBM_BUDGET,
+           "launch": {(f"{k[0]}d_L{k[1]}" if isinstance(k, tuple) else f"{k}d"): v
+                      for k, v in workloads.SERVE_LAUNCH.items()},
+           "hbm_budget_bytes": workloads.SERVE_HBM_BUDGET,
            "jobs_streamed_from_hbm": sum(1 for _, s in stream if s.dim == 3 and s.lx >= 48)}
     for name, realtime in (("poisson", True), ("saturation", False)):
         srv = serve.Server(hbm_budget_bytes=workloads.SERVE_HBM_BUDGET, n_therm=workloads.N_THERM,

@@ -78,7 +78,9 @@ class Server:
     """hbm_budget_bytes: device memory the resident arenas may hold.
     launch: ee_launch_cfg of the chunk launches (dict or None), or a dict
     {dimension: cfg}: each job then takes the shape of its dimension (the
-    server runs each shape's units in chunks of their own).
+    server runs each shape's units in chunks of their own); keys
+    (dimension, L) give the shape of the lattices of extent L in x and take
+    precedence over the dimension's.
     max_inflight, chunk_units: the native server's launch slots and units per
     chunk.  stream_slots: side streams (and worker threads) for jobs on the
     HBM-streaming path.
@@ -93,7 +95,8 @@ class Server:
         self.n_therm = n_therm
         self.keep_work = keep_work
         self.keep_spins = keep_spins
-        by_dim = isinstance(launch, dict) and set(launch) <= {2, 3}
+        by_dim = isinstance(launch, dict) and bool(launch) and all(
+            k in (2, 3) or (isinstance(k, tuple) and len(k) == 2 and k[0] in (2, 3)) for k in launch)
         self.launch_by_dim = launch if by_dim else {}
         self.native = ee.ee_server_create(None if by_dim else launch, n_therm, max_inflight, chunk_units)
         # Streams, all of default priority: the server's chunk slots and its
@@ -145,8 +148,10 @@ class Server:
             if ee.ee_job_on_chip(desc):
                 t0 = time.perf_counter()
                 job = ee.Job(req.spec, stream=self.upload)
-                if req.spec.dim in self.launch_by_dim:
-                    job.set_launch(self.launch_by_dim[req.spec.dim])
+                shape = self.launch_by_dim.get((req.spec.dim, req.spec.lx),
+                                               self.launch_by_dim.get(req.spec.dim))
+                if shape is not None:
+                    job.set_launch(shape)
                 t1 = time.perf_counter()
                 ee.ee_server_submit(self.native, job.handle)
                 t2 = time.perf_counter()

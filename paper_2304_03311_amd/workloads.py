@@ -40,14 +40,23 @@ BENCH_LAUNCH = {"block_threads": 64, "lds_bytes": 8192, "grid_blocks": 0, "use_g
 # 4096; the mix sets the offered load, about 70% of the served path's
 # measured capacity), the HBM admission budget (288 GB of HBM3E minus a
 # reserve for the rest of the process) and the launch shapes of the server's
-# chunk launches by dimension: 2D lattices in one-wave workgroups of up to
-# 4 KiB (the tuner's shapes for the 2D sets), 3D in 512-thread workgroups
-# (the tuner's shape for the 3D-heavy 24-job set)
+# chunk launches, by dimension and, for two 3D sizes, by lattice extent:
+# 2D lattices in one-wave workgroups of up to 4 KiB (the tuner's shapes for
+# the 2D sets), 3D in 512-thread workgroups (the tuner's shape for the
+# 3D-heavy 24-job set; one 32^3 trajectory each), except 24^3, one
+# trajectory per three-wave workgroup (96 row slots per replica, a multiple
+# of L_y: the parity-major row order, three steps per half-sweep, where 256
+# or 512 lanes take the lane-map order with a partly idle last pass), and
+# 16^3, one trajectory per one-wave workgroup (measured on an MI355X over
+# 8 jobs x 512 trajectories: 24^3 2353 against 2243 attempts/ns at 256
+# threads, 16^3 2579 against 2393 at 512 threads)
 SERVE_MIX = {"max_l3": 96, "n_traj_choices": (64, 256, 1024, 4096), "n_traj_weights": (0.54, 0.3, 0.125, 0.035),
              "n_step_choices": (500, 1000), "large_n_traj": (8, 16)}
 SERVE_HBM_BUDGET = 256 * 1024 ** 3
 SERVE_LAUNCH = {2: {"block_threads": 64, "lds_bytes": 4096, "grid_blocks": 0, "use_graph": 1, "flags": 0},
-                3: {"block_threads": 512, "lds_bytes": 54272, "grid_blocks": 0, "use_graph": 1, "flags": 0}}
+                3: {"block_threads": 512, "lds_bytes": 54272, "grid_blocks": 0, "use_graph": 1, "flags": 0},
+                (3, 24): {"block_threads": 192, "lds_bytes": 28672, "grid_blocks": 0, "use_graph": 1, "flags": 0},
+                (3, 16): {"block_threads": 64, "lds_bytes": 8192, "grid_blocks": 0, "use_graph": 1, "flags": 0}}
 
 
 def config1_job() -> JobSpec:

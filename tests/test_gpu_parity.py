@@ -260,6 +260,15 @@ ROW_ORDER_CASES = [
      dict(block_threads=64, lds_bytes=1024)),
     ("3d_paritymajor", dict(dim=3, lt=4, lx=32, ly=4, n=2, beta=BC3, l=9, n_step=6, n_traj=4, seed=72),
      dict(block_threads=64, lds_bytes=4096)),
+    # the serving shapes of the 3D lattices.  24^3 (27 KiB, G = W = 3,
+    # R = 576) in three-wave workgroups: B = 96, a multiple of ly = 24
+    # (parity-major, three steps of both classes per half-sweep).
+    ("3d_24cube_192", dict(dim=3, lt=24, lx=24, ly=24, n=2, beta=BC3, l=11, n_step=4, n_traj=3, seed=73,
+                           spin_format=1), dict(block_threads=192, lds_bytes=28672)),
+    # 16^3 (8 KiB, G = W = 2, R = 256) in one-wave workgroups: B = 32
+    # (parity-major, eight steps).
+    ("3d_16cube_64", dict(dim=3, lt=16, lx=16, ly=16, n=2, beta=BC3, l=5, n_step=5, n_traj=3, seed=74,
+                          spin_format=1, reverse=True), dict(block_threads=64, lds_bytes=8192)),
 ]
 
 

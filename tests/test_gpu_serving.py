@@ -75,6 +75,39 @@ def test_results_identical_alone_and_in_the_mix():
     assert any(not r.streamed for r in done)
 
 
+def test_shipped_serving_shapes_match_alone_and_oracle():
+    """The serving benchmark's launch shapes (by dimension, and by extent for
+    16^3 and 24^3, each size in chunks of its own shape): every job is
+    bit-identical to its run alone and to the oracle on its first
+    trajectory."""
+    specs = [ee.JobSpec(dim=3, lt=24, lx=24, ly=24, n=2, beta=0.23, l=7, n_step=6, n_traj=5, seed=501,
+                        spin_format=ee.EE_SPINS_BITPACKED),
+             ee.JobSpec(dim=3, lt=16, lx=16, ly=16, n=2, beta=workloads.BETA_3D, l=3, n_step=8, n_traj=9,
+                        seed=502, spin_format=ee.EE_SPINS_BITPACKED, reverse=True),
+             ee.JobSpec(dim=3, lt=32, lx=32, ly=32, n=2, beta=0.21, l=20, n_step=4, n_traj=3, seed=503,
+                        spin_format=ee.EE_SPINS_BITPACKED),
+             ee.JobSpec(dim=2, lt=64, lx=64, ly=1, n=2, beta=workloads.BETA_C_2D, l=30, n_step=10, n_traj=17,
+                        seed=504),
+             ee.JobSpec(dim=3, lt=24, lx=24, ly=24, n=2, beta=workloads.BETA_3D, l=0, n_step=3, n_traj=2,
+                        seed=505, spin_format=ee.EE_SPINS_BITPACKED)]
+    reqs = serve.requests_from_stream([(0.0, s) for s in specs])
+    srv = serve.Server(hbm_budget_bytes=1 << 34, n_therm=6, keep_work=True, keep_spins=True,
+                       launch=workloads.SERVE_LAUNCH)
+    say(f"[gpu] serving {len(reqs)} requests in the benchmark's shapes")
+    done = srv.run(reqs, realtime=False)
+    srv.close()
+    assert len(done) == len(reqs) and not any(r.streamed for r in done)
+    for req in done:
+        s = req.spec
+        say(f"[gpu]   check D={s.dim} L={s.lx} n_t={s.n_traj} N={s.n_step}")
+        r, w = alone(s, 6)
+        assert np.array_equal(req.work, w), s
+        assert req.result.dF == r.dF
+        I_or, sp_or = eo.run(oracle_job(s), 6, 0, 1, want_spins=True)
+        assert req.work[0] == I_or[0]
+        assert np.array_equal(req.spins, sp_or[0])
+
+
 def test_server_matches_batch_path_across_chunks():
     """Jobs whose units span several chunks (chunk_units = 3) give the batch
     path's bits."""

@@ -162,8 +162,8 @@ int main() {
     const JP P = make_jp(s.dim, s.lt, s.lx, s.ly, s.n, s.l);
     const int min_T = (P.G + 63) / 64 * 64;
     // on-chip launch shapes: block sizes and trajectories per workgroup
-    for (int block = 64; block <= 1024; block *= 2)
-      for (int k = 1; k <= 16; k *= 2) {
+    for (int block : {64, 128, 192, 256, 384, 512, 576, 768, 1024})
+      for (int k : {1, 2, 3, 4, 8, 16}) {
         const int T = block / k;
         if (T < P.G || block < min_T) continue;
         const int W = words_per_lane(P, T);
