@@ -50,7 +50,7 @@ BENCH_LAUNCH = {"block_threads": 64, "lds_bytes": 8192, "grid_blocks": 0, "use_g
 # 16^3, one trajectory per one-wave workgroup (measured on an MI355X over
 # 8 jobs x 512 trajectories: 24^3 2353 against 2243 attempts/ns at 256
 # threads, 16^3 2579 against 2393 at 512 threads)
-SERVE_MIX = {"max_l3": 96, "n_traj_choices": (64, 256, 1024, 4096), "n_traj_weights": (0.54, 0.3, 0.125, 0.035),
+SERVE_MIX = {"max_l3": 96, "n_traj_choices": (64, 256, 1024, 4096), "n_traj_weights": (0.48, 0.32, 0.155, 0.045),
              "n_step_choices": (500, 1000), "large_n_traj": (8, 16)}
 SERVE_HBM_BUDGET = 256 * 1024 ** 3
 SERVE_LAUNCH = {2: {"block_threads": 64, "lds_bytes": 4096, "grid_blocks": 0, "use_graph": 1, "flags": 0},
