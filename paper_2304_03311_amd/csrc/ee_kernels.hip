@@ -166,9 +166,32 @@ __device__ __forceinline__ uint32_t min_u16x2(uint32_t a, uint32_t b) {
 // consecutive LDS banks; W separate dword accesses at a lane stride of W
 // words would conflict W-fold.  W = 3 (rows of three words, one lane per
 // row) reads dwords: an odd lane stride does not conflict.
-template <int W>
+// GM: p points into device memory (the HBM-streaming path).  The access is
+// then made through a global-address-space pointer: a flat access, which is
+// what a pointer of unknown space compiles to, also counts against the
+// LDS/scalar wait counter, so every LDS or scalar wait would drain the HBM
+// loads in flight.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) u32x2 g_u32x2;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+
+template <bool GM>
+__device__ __forceinline__ uint32_t ld_word(const uint32_t* p) {
+  if constexpr (GM) return *(const g_u32*)p;
+  else return *p;
+}
+
+template <int W, bool GM = false>
 __device__ __forceinline__ void ld_words(const uint32_t* p, uint32_t v[W]) {
-  if constexpr (W == 4) {
+  if constexpr (GM && W == 4) {
+    const u32x4 x = *(const g_u32x4*)p;
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else if constexpr (GM && W == 2) {
+    const u32x2 x = *(const g_u32x2*)p;
+    v[0] = x.x; v[1] = x.y;
+  } else if constexpr (W == 4) {
     const uint4 x = *reinterpret_cast<const uint4*>(p);
     v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
   } else if constexpr (W == 2) {
@@ -176,12 +199,19 @@ __device__ __forceinline__ void ld_words(const uint32_t* p, uint32_t v[W]) {
     v[0] = x.x; v[1] = x.y;
   } else {
 #pragma unroll
-    for (int q = 0; q < W; ++q) v[q] = p[q];
+    for (int q = 0; q < W; ++q) v[q] = ld_word<GM>(p + q);
   }
 }
-template <int W>
+template <int W, bool GM = false>
 __device__ __forceinline__ void st_words(uint32_t* p, const uint32_t v[W]) {
-  if constexpr (W == 4) {
+  if constexpr (GM && W == 4) {
+    *(g_u32x4*)p = u32x4{v[0], v[1], v[2], v[3]};
+  } else if constexpr (GM && W == 2) {
+    *(g_u32x2*)p = u32x2{v[0], v[1]};
+  } else if constexpr (GM) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) *(g_u32*)(p + q) = v[q];
+  } else if constexpr (W == 4) {
     *reinterpret_cast<uint4*>(p) = make_uint4(v[0], v[1], v[2], v[3]);
   } else if constexpr (W == 2) {
     *reinterpret_cast<uint2*>(p) = make_uint2(v[0], v[1]);
@@ -219,7 +249,7 @@ __device__ __forceinline__ uint32_t half16(uint32_t word, int hi) { return hi ? 
 // same row in sweep g_next with counter word c3_next into nextU.  They do
 // not depend on spins, so that chain overlaps this row's loads and
 // decisions instead of lengthening the next half-sweep.
-template <int DIM, bool FULL, int W, int PAR, bool CUT, bool XG = false, bool LA = false>
+template <int DIM, bool FULL, int W, int PAR, bool CUT, bool XG = false, bool LA = false, bool GM = false>
 __device__ __forceinline__ void row_update(const JP& P, const int w, const int wl, const int wr,
                                            uint32_t* __restrict__ Lc, const uint32_t* __restrict__ Lo,
                                            const uint32_t* __restrict__ thr, const int c, const uint32_t g,
@@ -240,14 +270,14 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   const uint32_t rshift = (w == G - 1) ? (uint32_t)tailsh : 24u;
   const int p = (PAR >= 0) ? PAR : ((c + t + y) & 1);  // x parity of this row's sites
   uint32_t A[W], B[W], S[W], a[W];
-  ld_words<W>(pO, A);
+  ld_words<W, GM>(pO, A);
   if (LA) {
 #pragma unroll
     for (int k = 0; k < NC; ++k) philox10_x02(c0 + k, g_next, j, c3_next, P.key0, P.key1, 0x80008000u, nextU + 4 * k);
   }
   if (FULL) {
     // the sites' x-1 (p = 0) or x+1 (p = 1) neighbours straddle two words
-    const uint32_t E = pO[(p ? wr : wl) - w];
+    const uint32_t E = ld_word<GM>(pO + ((p ? wr : wl) - w));
     const uint32_t sh = p ? 1u : 3u;
 #pragma unroll
     for (int q = 0; q < W; ++q) {
@@ -256,22 +286,22 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
       B[q] = __builtin_amdgcn_alignbyte(p ? nxt : A[q], p ? A[q] : prv, sh);
     }
   } else {
-    const uint32_t nb = pO[(p ? wr : wl) - w];
+    const uint32_t nb = ld_word<GM>(pO + ((p ? wr : wl) - w));
     const uint32_t Br = (A[0] >> 8) | ((nb & 0xFFu) << rshift);
     const uint32_t Bl = (A[0] << 8) | ((w == 0) ? ((nb >> tailsh) & 0xFFu) : (nb >> 24));
     B[0] = p ? Br : Bl;
   }
   // t -+ 1 neighbours
   uint32_t Tm[W], Tp[W];
-  ld_words<W>(pC, S);
-  ld_words<W>(pO + tmo, Tm);
-  ld_words<W>(pO + tpo, Tp);
+  ld_words<W, GM>(pC, S);
+  ld_words<W, GM>(pO + tmo, Tm);
+  ld_words<W, GM>(pO + tpo, Tp);
 #pragma unroll
   for (int q = 0; q < W; ++q) a[q] = xad_op(A[q], S[q], xad_op(B[q], S[q], xad_op(Tm[q], S[q], Tp[q] ^ S[q])));
   if (DIM == 3) {
     uint32_t Ym[W], Yp[W];
-    ld_words<W>(pO + ymo, Ym);
-    ld_words<W>(pO + ypo, Yp);
+    ld_words<W, GM>(pO + ymo, Ym);
+    ld_words<W, GM>(pO + ypo, Yp);
 #pragma unroll
     for (int q = 0; q < W; ++q) a[q] = xad_op(Ym[q], S[q], xad_op(Yp[q], S[q], a[q]));
   }
@@ -287,7 +317,7 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
   const auto gmq = [&](int q) { return (PAR >= 0) ? gm_in[q] : glued_mask(P.l - p - 8 * (w + q)); };
   if (cutrow) {
     const int og = (PAR >= 0 || XG) ? og_in : glued_row(P, r, t, y) * G + w;
-    ld_words<W>(Lo + og, Tgl);
+    ld_words<W, GM>(Lo + og, Tgl);
 #pragma unroll
     for (int q = 0; q < W; ++q) {
       Tcu[q] = (t == 0) ? Tp[q] : Tm[q];
@@ -451,14 +481,15 @@ __device__ __forceinline__ void row_update(const JP& P, const int w, const int w
     // S ^ ((f >> 7) & fmask) in one three-input op (table 0x78 = a ^ (b & c))
     Snew[q] = __builtin_amdgcn_bitop3_b32(S[q], f[q] >> 7, fmask, 0x78);
   }
-  st_words<W>(pC, Snew);
+  st_words<W, GM>(pC, Snew);
 }
 
 // One half-sweep of colour c over the lane's rows of one trajectory, in the
 // order of the lane map (any map; the streaming path's and the general
 // on-chip one).  L: the trajectory (two colour planes).  UJ: the
-// trajectory index is uniform per wave.
-template <int DIM, bool FULL, bool UJ, int W>
+// trajectory index is uniform per wave.  GM: L is in device memory (the
+// streaming path), accessed through global-address-space pointers.
+template <int DIM, bool FULL, bool UJ, int W, bool GM = false>
 __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t* __restrict__ L,
                                            const uint32_t* __restrict__ thr, const int c,
                                            const uint32_t g, uint32_t j, const int pos, const int dpos,
@@ -484,9 +515,9 @@ __device__ __forceinline__ void half_sweep(const JP& P, const Lane& ln, uint32_t
     const uint32_t c0 = (uint32_t)((t * P.ly + y) * P.G8 + (w >> 1));
     const auto row = [&](auto cut) {
       const int tmo = -LyG + ((decltype(cut)::value && t == 0) ? ltLyG : 0);
-      row_update<DIM, FULL, W, -1, decltype(cut)::value>(P, w, ln.wl, ln.wr, Lc, Lo, thr, c, g, j, pos, dpos, work,
-                                                         dI, r, t, y, Lc + rowbase + w, Lo + rowbase + w, tmo, tpo,
-                                                         ymo, ypo, c0, ctr3 | ((uint32_t)r << 1));
+      row_update<DIM, FULL, W, -1, decltype(cut)::value, false, false, GM>(
+          P, w, ln.wl, ln.wr, Lc, Lo, thr, c, g, j, pos, dpos, work, dI, r, t, y, Lc + rowbase + w, Lo + rowbase + w,
+          tmo, tpo, ymo, ypo, c0, ctr3 | ((uint32_t)r << 1));
     };
     // the code for rows next to the cut runs only where some lane of the
     // wave has such a row
@@ -902,7 +933,8 @@ __device__ __forceinline__ void stream_half(const JP& P, uint32_t* s_thr, int la
   uint32_t* L = P.spins + (size_t)j * P.traj_words;
   int dI = 0;
   const Lane ln = make_lane(P, lt_ < lanes ? lt_ : 0, lanes, W, false);
-  if (lt_ < lanes && ln.kstart < ln.kend) half_sweep<DIM, FULL, true, W>(P, ln, L, s_thr, c, g, j, pos, dpos, work, dI);
+  if (lt_ < lanes && ln.kstart < ln.kend)
+    half_sweep<DIM, FULL, true, W, true>(P, ln, L, s_thr, c, g, j, pos, dpos, work, dI);
   if (dI != 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.work[j]), (unsigned long long)(long long)dI);
 }
 
