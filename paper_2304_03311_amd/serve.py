@@ -74,6 +74,19 @@ class ServeStats:
                 "last_streamed_done_s": self.last_streamed_s, "host_s": self.host_s}
 
 
+def is_shape_map(launch) -> bool:
+    """Whether `launch` maps dimensions (2, 3) or (dimension, L) pairs to
+    launch shapes, rather than being one shape."""
+    return isinstance(launch, dict) and bool(launch) and all(
+        k in (2, 3) or (isinstance(k, tuple) and len(k) == 2 and k[0] in (2, 3)) for k in launch)
+
+
+def launch_shape(shape_map: dict, spec: ee.JobSpec):
+    """The launch shape of a job under a shape map: its (dimension, L)
+    entry, else its dimension's, else None (the server's own shape)."""
+    return shape_map.get((spec.dim, spec.lx), shape_map.get(spec.dim))
+
+
 class Server:
     """hbm_budget_bytes: device memory the resident arenas may hold.
     launch: ee_launch_cfg of the chunk launches (dict or None), or a dict
@@ -95,8 +108,7 @@ class Server:
         self.n_therm = n_therm
         self.keep_work = keep_work
         self.keep_spins = keep_spins
-        by_dim = isinstance(launch, dict) and bool(launch) and all(
-            k in (2, 3) or (isinstance(k, tuple) and len(k) == 2 and k[0] in (2, 3)) for k in launch)
+        by_dim = is_shape_map(launch)
         self.launch_by_dim = launch if by_dim else {}
         self.native = ee.ee_server_create(None if by_dim else launch, n_therm, max_inflight, chunk_units)
         # Streams, all of default priority: the server's chunk slots and its
@@ -148,8 +160,7 @@ class Server:
             if ee.ee_job_on_chip(desc):
                 t0 = time.perf_counter()
                 job = ee.Job(req.spec, stream=self.upload)
-                shape = self.launch_by_dim.get((req.spec.dim, req.spec.lx),
-                                               self.launch_by_dim.get(req.spec.dim))
+                shape = launch_shape(self.launch_by_dim, req.spec)
                 if shape is not None:
                     job.set_launch(shape)
                 t1 = time.perf_counter()
