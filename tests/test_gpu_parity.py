@@ -517,6 +517,28 @@ def test_full_size_streaming_96cube_sampled():
         job.close()
 
 
+def test_full_size_serving_shapes_3d_sampled():
+    """The serving benchmark's own 3D shapes at full size: 24^3 in three-wave
+    workgroups (parity-major rows) and 16^3 in one-wave workgroups, each
+    with N = 1000 after the benchmark's thermalisation, 256 trajectories in
+    one persistent launch of its shape; the first and the last trajectory
+    against the oracle, and the estimate."""
+    for L in (24, 16):
+        s = ee.JobSpec(dim=3, lt=L, lx=L, ly=L, n=2, beta=workloads.BETA_3D, l=L // 3, n_step=1000, n_traj=256,
+                       seed=600 + L, spin_format=ee.EE_SPINS_BITPACKED)
+        launch = workloads.SERVE_LAUNCH[(3, L)]
+        say(f"[gpu] full {L}^3 in the serving shape {launch}")
+        job = ee.Job(s)
+        ee.batch_run([job], workloads.N_THERM, cfg=launch)
+        for j in (0, s.n_traj - 1):
+            say(f"[gpu]   sample j={j}")
+            I_or, sp_or = eo.run(oracle_job(s), workloads.N_THERM, j, j + 1, want_spins=True)
+            assert job.work()[j] == I_or[0]
+            assert np.array_equal(job.spins(j + 1)[j], sp_or[0])
+        check_estimate(job.estimate(), job.work(), s, f"{L}^3 serving shape")
+        job.close()
+
+
 def test_full_size_24_uneven_jobs_sampled():
     """The 24 uneven jobs (2D L = 24..96, 3D L = 16..32, N = 500..2000) in one
     persistent launch of the benchmark's shape: one sampled trajectory of
