@@ -291,6 +291,33 @@ def test_both_row_orders_match_oracle(name, kw, cfg):
     jobs[0].close()
 
 
+# The lattice, order and beta at which a since-removed 64-VGPR build of the
+# sweep kernel gave wrong protocol results: 8x8, n = 2, one word per row
+# (lane-map order), beta = 0 (every attempt flips, so a skipped or repeated
+# site shows in the spins and the work).  The shipped kernel at every block
+# size and several trajectory counts per workgroup, on both paths.
+BETA0_CFGS = [dict(block_threads=b, lds_bytes=l) for b in (64, 128, 256, 512, 1024) for l in (256, 1024, 4096)]
+
+
+@pytest.mark.parametrize("cfg", BETA0_CFGS, ids=[f"b{c['block_threads']}_lds{c['lds_bytes']}" for c in BETA0_CFGS])
+def test_beta0_lanemap_every_block_size(cfg):
+    s = ee.JobSpec(dim=2, lt=8, lx=8, ly=1, n=2, beta=0.0, l=3, n_step=40, n_traj=9, seed=8)
+    say(f"[gpu] beta = 0 lane map, launch {cfg}")
+    I_or, sp_or = eo.run(oracle_job(s), 3, want_spins=True)
+    j = ee.Job(s)
+    j.set_launch(cfg)
+    j.thermalize(3)
+    j.run_protocol()
+    assert np.array_equal(j.work(), I_or)
+    assert np.array_equal(j.spins(), sp_or)
+    j.close()
+    jobs = [ee.Job(s)]
+    ee.batch_run(jobs, 3, cfg=cfg)
+    assert np.array_equal(jobs[0].work(), I_or)
+    assert np.array_equal(jobs[0].spins(), sp_or)
+    jobs[0].close()
+
+
 @pytest.mark.parametrize("cfg", [dict(block_threads=64), dict(block_threads=128), dict()])
 def test_rows_wider_than_the_requested_block(cfg):
     # lx = 2048: 256 words per row; a 64-thread block is raised to 256 so
