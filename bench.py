@@ -172,7 +172,10 @@ def configs_run() -> dict:
         launch = autotune.cached(specs, n_therm) or autotune.tune(specs, n_therm)
         jobs = [ee.Job(s) for s in specs]
         att = sum(s.n_traj * s.sites * (n_therm + s.n_step) for s in specs)
-        dt, kms, res = _time_batch(jobs, n_therm, launch)
+        # the best of several runs; ten for the sub-millisecond set, whose
+        # wall time varies by tens of microseconds from run to run
+        reps = 10 if att < 10 ** 9 else 2
+        dt, kms, res = _time_batch(jobs, n_therm, launch, reps=reps)
         dtp, _ = _time_per_job(jobs, n_therm)
         out[name] = {"jobs": len(specs), "attempts": att, "batched_ms": dt * 1e3,
                      "batched_attempts_per_ns": att / (dt * 1e9), "kernel_ms": kms,

@@ -486,6 +486,25 @@ def test_full_size_2d_64x64_batch_sampled():
         j.close()
 
 
+def test_full_size_2d_16x16_bench_launch():
+    """The 16x16 job (64 trajectories, N = 256 after 100 thermalisation
+    sweeps) in the launch the benchmark times (the tuner's choice: one-wave
+    workgroups, no graph): every trajectory's work and final spins against
+    the oracle, then a second run on the same arena gives the same bits."""
+    s = workloads.config1_job()
+    launch = _bench_launch([s])
+    say(f"[gpu] 16x16 job, launch {launch}")
+    I_or, sp_or = eo.run(oracle_job(s), workloads.N_THERM, want_spins=True)
+    job = ee.Job(s)
+    for rep in range(2):
+        job.reset()
+        ee.batch_run([job], workloads.N_THERM, cfg=launch)
+        assert np.array_equal(job.work(), I_or)
+        assert np.array_equal(job.spins(), sp_or)
+    check_estimate(job.estimate(), I_or, s, "16x16")
+    job.close()
+
+
 def test_full_size_3d_32cube_sampled():
     """The 3D 32^3 bit-packed job through the per-job path and through the
     batched launch shape the benchmark times."""
